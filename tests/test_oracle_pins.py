@@ -1,0 +1,162 @@
+"""Pins for the CPU oracle (no GPU).  Each test checks the oracle against
+something other than itself: exact brute force, a closed form, an independent
+algorithm, or an identity the mathematics fixes."""
+import numpy as np
+import pytest
+
+from oracle import closed_forms, dense, exact, rgf
+from paper_1104_0623_amd import inputs
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def problem(Nx, Ny, stencil, seed, E, fL=1.0, fR=0.3, vmax=0.7):
+    p = inputs.make_problem(Nx, Ny, stencil, vmax=vmax, seed=seed, energies=[E], fL=fL, fR=fR)
+    return p
+
+
+TINY = [(2, 2, 5, 0, 0.31 + 0.05j), (3, 3, 5, 1, -0.7 + 1e-3j), (3, 2, 9, 2, 1.1 + 0.02j),
+        (1, 5, 5, 3, 0.2 + 1e-2j), (4, 3, 9, 4, -1.9 + 1e-3j), (2, 4, 9, 5, 0.05 + 1e-6j)]
+
+
+@pytest.mark.parametrize("Nx,Ny,stencil,seed,E", TINY)
+def test_dense_matches_exact_bruteforce(Nx, Ny, stencil, seed, E):
+    p = problem(Nx, Ny, stencil, seed, E)
+    d = dense.dense_solve(Nx, Ny, stencil, p["H"], p["energies"], p["sigma"], p["sigma_less"])
+    bi, bj, _, _ = inputs.bond_endpoints(Nx, Ny, stencil)
+    dG, dGl, bonds = exact.exact_solve(Nx, Ny, p["H"], E, p["sigma"][0], p["sigma_less"][0],
+                                       list(zip(bi.tolist(), bj.tolist())))
+    assert rel(d["diag_G"][0].ravel(), dG) < 1e-12
+    assert rel(d["diag_Gless"][0].ravel(), dGl) < 1e-12
+    if bonds:
+        bG = np.array([b[0] for b in bonds]); bL = np.array([b[1] for b in bonds])
+        bJ = np.array([b[2] for b in bonds])
+        assert rel(d["bond_G"][0], bG) < 1e-12
+        assert rel(d["bond_Gless"][0], bL) < 1e-12
+        assert rel(d["bond_J"][0], bJ) < 1e-11
+
+
+def test_exact_catches_planted_sign_error():
+    """A plausible mistake (wrong hop sign) must fail the brute-force pin."""
+    Nx, Ny, stencil, seed, E = 3, 3, 5, 1, -0.7 + 1e-3j
+    p = problem(Nx, Ny, stencil, seed, E)
+    Hbad = p["H"].copy(); Hbad[1:] *= -1.0
+    d = dense.dense_solve(Nx, Ny, stencil, Hbad, p["energies"], p["sigma"], p["sigma_less"])
+    dG, _, _ = exact.exact_solve(Nx, Ny, p["H"], E, p["sigma"][0], p["sigma_less"][0], [])
+    assert rel(d["diag_G"][0].ravel(), dG) > 1e-3
+
+
+@pytest.mark.parametrize("Nx,Ny,E", [(6, 5, 0.37 + 1e-3j), (5, 9, -1.2 + 1e-4j), (9, 4, 2.6 + 1e-3j),
+                                     (1, 7, 0.5 + 1e-3j), (1, 3, -2.5 + 1e-2j)])
+def test_clean_ribbon_closed_form(Nx, Ny, E):
+    p = inputs.make_problem(Nx, Ny, 5, vmax=0.0, energies=[E])
+    ref = closed_forms.ribbon_local_G(Nx, E)
+    d = dense.dense_solve(Nx, Ny, 5, p["H"], p["energies"], p["sigma"], p["sigma_less"], bonds=False)
+    r = rgf.rgf_solve(Nx, Ny, 5, p["H"], p["energies"], p["sigma"], p["sigma_less"], bonds=False)
+    for y in range(Ny):
+        assert rel(d["diag_G"][0, y], ref) < 1e-12
+        assert rel(r["diag_G"][0, y], ref) < 1e-12
+
+
+def test_clean_ribbon_transmission_counts_open_modes():
+    Nx, Ny = 7, 6
+    for E in (0.3, -1.1, 2.2, 3.9):
+        p = inputs.make_problem(Nx, Ny, 5, vmax=0.0, energies=[E + 1e-7j])
+        T = dense.transmission(Nx, Ny, p["H"], E + 1e-7j, p["sigma"][0])
+        assert abs(T - closed_forms.ribbon_open_modes(Nx, E)) < 1e-4
+
+
+@pytest.mark.parametrize("Nx,Ny,stencil,seed", [(8, 7, 5, 11), (6, 9, 9, 12), (1, 6, 5, 13), (5, 1, 9, 14),
+                                                (4, 4, 5, 15)])
+def test_rgf_matches_dense(Nx, Ny, stencil, seed):
+    E = np.array([0.3 + 1e-6j, -2.1 + 1e-6j, 1.7 + 1e-3j])
+    p = inputs.make_problem(Nx, Ny, stencil, vmax=1.0, seed=seed, energies=E, fL=1.0, fR=0.25)
+    d = dense.dense_solve(Nx, Ny, stencil, p["H"], E, p["sigma"], p["sigma_less"])
+    r = rgf.rgf_solve(Nx, Ny, stencil, p["H"], E, p["sigma"], p["sigma_less"])
+    for k in ("diag_G", "diag_Gless", "bond_G", "bond_Gless"):
+        for e in range(E.size):
+            assert rel(r[k][e], d[k][e]) < 1e-10, k
+    # J is normalised by its own scale plus |H| |G<| (J can be ~0 in degenerate meshes)
+    hmax = np.max(np.abs(p["H"][1:]))
+    for e in range(E.size):
+        scale = np.max(np.abs(d["bond_J"][e])) + hmax * np.max(np.abs(d["bond_Gless"][e]))
+        assert np.max(np.abs(r["bond_J"][e] - d["bond_J"][e])) <= 1e-10 * scale
+
+
+def test_identities_symmetry_and_antihermitian():
+    Nx, Ny, stencil = 5, 6, 9
+    E = np.array([0.45 + 1e-6j])
+    p = inputs.make_problem(Nx, Ny, stencil, vmax=1.0, seed=3, energies=E, fL=1.0, fR=0.0)
+    d = dense.dense_solve(Nx, Ny, stencil, p["H"], E, p["sigma"], p["sigma_less"], keep_G=True)
+    G, Gl = d["G"][0], d["Gless"][0]
+    assert rel(G, G.T) < 1e-12                         # A = A^T  =>  G = G^T
+    assert rel(Gl, -Gl.conj().T) < 1e-12               # G< anti-Hermitian
+    assert np.max(np.abs(d["diag_Gless"][0].real)) < 1e-12 * np.max(np.abs(d["diag_Gless"][0]))
+    assert np.min(d["diag_Gless"][0].imag) > -1e-12    # density -i G<_ii >= 0
+
+
+def test_eta_corrected_equilibrium_identity():
+    """With f_L = f_R = f:  -f (G - G^dagger) = G Sigma< G^dagger + 2 i eta f G G^dagger,
+    because A^dagger - A = Sigma - Sigma^dagger - 2 i eta I."""
+    Nx, Ny, f, eta = 6, 7, 0.5, 1e-3
+    E = np.array([0.2 + 1j * eta])
+    p = inputs.make_problem(Nx, Ny, 5, vmax=0.5, seed=4, energies=E, fL=f, fR=f)
+    d = dense.dense_solve(Nx, Ny, 5, p["H"], E, p["sigma"], p["sigma_less"], keep_G=True)
+    G, Gl = d["G"][0], d["Gless"][0]
+    lhs = -f * (G - G.conj().T)
+    rhs = Gl + 2j * eta * f * (G @ G.conj().T)
+    assert rel(lhs, rhs) < 1e-11
+    # without the eta term the identity fails at O(eta)
+    assert rel(lhs, Gl) > 1e-6
+
+
+def test_current_conservation_and_cut_sum():
+    Nx, Ny, stencil, eta = 5, 8, 9, 1e-6
+    E = 0.35 + 1j * eta
+    p = inputs.make_problem(Nx, Ny, stencil, vmax=0.8, seed=5, energies=[E], fL=1.0, fR=0.0)
+    d = dense.dense_solve(Nx, Ny, stencil, p["H"], p["energies"], p["sigma"], p["sigma_less"])
+    bi, bj, _, _ = inputs.bond_endpoints(Nx, Ny, stencil)
+    J = d["bond_J"][0]
+    n = Nx * Ny
+    out = np.zeros(n)
+    np.add.at(out, bi, J)
+    np.add.at(out, bj, -J)
+    dens = d["diag_Gless"][0].ravel()
+    xs = np.arange(n) % Nx
+    ys = np.arange(n) // Nx
+    inner = (ys > 0) & (ys < Ny - 1)
+    # local balance off the contact columns: sum_j J_{i->j} = -2 eta Im G<_ii
+    assert np.max(np.abs(out[inner] + 2 * eta * dens[inner].imag)) < 1e-10
+    T = dense.transmission(Nx, Ny, p["H"], E, p["sigma"][0])
+    for ycut in range(Ny - 1):
+        cross = (ys[bi] <= ycut) & (ys[bj] > ycut)
+        flow = J[cross].sum()
+        assert abs(flow - T) < 1e-4 * max(T, 1.0)
+    assert T > 0.1
+
+
+def test_lead_self_energy_is_retarded():
+    for E in (0.3 + 1e-6j, -3.0 + 1e-6j, 2.5 + 1e-6j, -0.1 + 0.2j):
+        S = inputs.lead_self_energy(7, E)
+        gamma = 1j * (S - S.conj().T)
+        assert np.min(np.linalg.eigvalsh(gamma)) > -1e-12
+        assert rel(S, S.T) < 1e-14
+
+
+@pytest.mark.parametrize("name", ["exact_3x3_5pt", "exact_3x2_9pt"])
+def test_dense_matches_golden_fixture(name):
+    import json, os
+    rec = json.load(open(os.path.join(os.path.dirname(__file__), "golden", name + ".json")))
+    c = rec["case"]
+    E = complex(*c["E"])
+    p = inputs.make_problem(c["Nx"], c["Ny"], c["stencil"], vmax=0.5, seed=c["seed"], energies=[E],
+                            fL=c["fL"], fR=c["fR"])
+    d = dense.dense_solve(c["Nx"], c["Ny"], c["stencil"], p["H"], p["energies"], p["sigma"], p["sigma_less"])
+    cz = lambda L: np.array([complex(a, b) for a, b in L])
+    assert rel(d["diag_G"][0].ravel(), cz(rec["diag_G"])) < 1e-12
+    assert rel(d["diag_Gless"][0].ravel(), cz(rec["diag_Gless"])) < 1e-12
+    assert rel(d["bond_G"][0], cz(rec["bond_G"])) < 1e-12
+    assert rel(d["bond_Gless"][0], cz(rec["bond_Gless"])) < 1e-12

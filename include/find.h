@@ -1,0 +1,172 @@
+/*
+ * libfind -- FIND selected inversion on AMD MI355X (gfx950).
+ *
+ * For every energy E of a batch, with the n x n matrix
+ *     A(E) = E*I - H - Sigma_L(E) - Sigma_R(E)         (n = Nx*Ny)
+ * the library returns diag(G), diag(G<), and the nearest-neighbour entries of
+ * G and G< with the bond currents, where G = A^{-1} and
+ * G< = G Sigma< G^dagger (paper, Sec. 1, NEGF equations; Sec. 3.1 for diag G<,
+ * Sec. 3.2 for the off-diagonal entries used for current density).  The
+ * method is FIND: a nested-dissection upward pass over the basic cluster tree
+ * (procedure updateBoundaryNodes), a downward pass over the complement
+ * clusters (procedure updateAdjacentNodes), both by the Schur-complement
+ * update of eq. (major-update) and the Sigma update of eq. (gless-update-rule),
+ * followed by a per-leaf extraction (eq. (cd1)-(cd3) and eq. (gless-nn)),
+ * as in procedure computeG<.
+ *
+ * Data conventions (all arrays dense, C order, complex = two doubles re,im):
+ *   mesh node (x, y), x in [0,Nx) transverse, y in [0,Ny) transport,
+ *   linear index i = y*Nx + x; contacts on the columns y = 0 (left, contact 0)
+ *   and y = Ny-1 (right, contact 1).
+ *   H          double [nst][Ny][Nx], nst = 3 (5-point) or 5 (9-point):
+ *              [0] on-site H_ii, [1] H between (x,y),(x+1,y), [2] (x,y),(x,y+1),
+ *              [3] (x,y),(x+1,y+1), [4] (x+1,y),(x,y+1).  H must be real
+ *              symmetric (the stored value is used for both H_ij and H_ji).
+ *   energies   complex [nE]   (E + i*eta, eta > 0)
+ *   sigma      complex [nE][2][Nx][Nx]: sigma[e][c][a][b] = Sigma_c(row a, col b)
+ *   sigma_less complex [nE][2][Nx][Nx], same layout (Sigma<_c)
+ *   diag_G, diag_Gless   complex [nE][Ny][Nx]
+ *   bond_G, bond_Gless   complex [nE][nbonds]  (G_ij and G<_ij, i first node)
+ *   bond_J               double  [nE][nbonds]  (J_{i->j} = 2 Re(H_ij G<_ji))
+ *   Bonds are numbered family by family: x-bonds [Ny][Nx-1] (i=(x,y), j=(x+1,y)),
+ *   y-bonds [Ny-1][Nx] (i=(x,y), j=(x,y+1)), and for 9-point meshes
+ *   d+ bonds [Ny-1][Nx-1] (i=(x,y), j=(x+1,y+1)) and d- bonds [Ny-1][Nx-1]
+ *   (i=(x+1,y), j=(x,y+1)).  find_n_bonds() gives nbonds.
+ *
+ * Memory and threading: every pointer passed to find_solve is a DEVICE
+ * pointer on the current HIP device, owned by the caller; the library never
+ * frees or keeps caller pointers past the call.  find_solve only enqueues work
+ * on the given HIP stream (NULL = default stream) and returns; outputs are
+ * valid once that stream has been synchronised.  A plan owns its device
+ * workspace and tree maps (allocated on first use on a device); calls that
+ * share a plan must be serialised by the caller (one stream at a time).
+ * No function throws across this boundary; errors are returned as
+ * find_status and described by find_last_error() (thread-local string).
+ */
+#ifndef FIND_H_
+#define FIND_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct find_plan_s* find_plan;
+
+typedef enum {
+  FIND_OK = 0,
+  FIND_E_ARG = 1,         /* invalid argument (sizes, NULL pointers, stencil) */
+  FIND_E_NOMEM = 2,       /* device allocation failed / over budget            */
+  FIND_E_SINGULAR = 3,    /* exactly zero pivot met (see find_sync_status)      */
+  FIND_E_DEVICE = 4,      /* HIP runtime error                                  */
+  FIND_E_UNSUPPORTED = 5  /* shape beyond what the kernels support             */
+} find_status;
+
+typedef enum { FIND_PREC_FP64 = 0, FIND_PREC_MIXED = 1 } find_precision;
+
+/* Plan options; pass NULL for defaults.
+ *   leaf          largest leaf-cluster side (default 8): the mesh is bisected
+ *                 along its longer side (y on ties) until both sides <= leaf
+ *                 (paper Sec. 2.1, the nested-dissection partition).
+ *   precision     FIND_PREC_FP64 (default) or FIND_PREC_MIXED.
+ *   max_energies  energies processed per internal pass (0 = chosen from the
+ *                 workspace budget).
+ *   workspace_budget  device bytes the plan may hold (0 = 64 GiB). */
+typedef struct {
+  int leaf;
+  int precision;
+  int max_energies;
+  int reserved0;
+  size_t workspace_budget;
+  int reserved[8];
+} find_plan_opts;
+
+/* Build the cluster tree, boundary sets, gather maps and level schedule for
+ * an Nx x Ny mesh with a 5- or 9-point stencil and dense contact columns
+ * (paper Sec. 2.1-2.2 for the trees and sets; procedure computeG<).  Host
+ * only; device state is created on first find_solve.
+ * Errors: FIND_E_ARG if Nx < 1, Ny < 1, stencil not 5/9, out == NULL,
+ * or leaf < 1. */
+find_status find_plan_create(int Nx, int Ny, int stencil, const find_plan_opts* opts,
+                             find_plan* out);
+
+/* Release the plan and all device memory it holds.  NULL is accepted. */
+find_status find_plan_destroy(find_plan plan);
+
+/* Device bytes one find_solve over nE energies holds (plan maps + energy
+ * pool + elimination workspace); for serving admission.  want_bonds selects
+ * the leaf extraction that also yields the bond entries. */
+find_status find_plan_footprint(find_plan plan, int nE, int want_bonds, size_t* bytes);
+
+/* Algorithmic real flops per energy (8 per complex multiply-add): for each
+ * elimination with s eliminated and b kept nodes, s^3/3 + 2 s^2 b + 3 s b^2
+ * complex multiply-adds (LU of A(S,S), L = A(B,S) A(S,S)^-1, the Schur update
+ * of eq. (major-update) and the two products of eq. (gless-update-rule)
+ * arranged as W = [-L, I] Sigma, R = W [-L, I]^dagger); plus 3 b'^3 for each
+ * final leaf block of size b' (inverse and G Sigma G^dagger). */
+find_status find_plan_flops(find_plan plan, int want_bonds, double* flops_per_energy);
+
+/* Number of bonds (output length per energy of bond_G/bond_Gless/bond_J). */
+int find_n_bonds(int Nx, int Ny, int stencil);
+
+/* Enqueue the whole FIND solve for nE energies on `hip_stream`.
+ * Inputs and outputs are device pointers in the layouts above.  diag_G and
+ * diag_Gless are required; bond_G, bond_Gless and bond_J may each be NULL
+ * (if all three are NULL the cheaper diagonal-only leaf extraction runs).
+ * Errors: FIND_E_ARG (nE < 1, NULL required pointer), FIND_E_NOMEM,
+ * FIND_E_DEVICE, FIND_E_UNSUPPORTED (a front larger than the kernels
+ * handle).  Pivot breakdown is reported by find_sync_status. */
+find_status find_solve(find_plan plan, int nE, const double* energies, const double* H,
+                       const double* sigma, const double* sigma_less, double* diag_G,
+                       double* diag_Gless, double* bond_G, double* bond_Gless, double* bond_J,
+                       void* hip_stream);
+
+/* Wait for `hip_stream`, then report FIND_E_SINGULAR if the last solve on
+ * this plan met an exactly-zero pivot (the energy index is in
+ * find_last_error()), else FIND_OK. */
+find_status find_sync_status(find_plan plan, void* hip_stream);
+
+/* Thread-local description of the last error of this thread. */
+const char* find_last_error(void);
+
+/* ---- Introspection (host only; for tests and tools) ---------------------- */
+typedef struct {
+  int Nx, Ny, stencil, leaf;
+  int n_clusters, depth, n_leaves;
+  int n_elims, n_stages, map_len;
+  int n_leafout, n_outbonds, n_outnodes;
+  int max_n, max_s, max_b;
+  int64_t pool_per_energy; /* complex elements per energy */
+  int reserved[8];
+} find_plan_summary_t;
+
+/* Field layout of one exported elimination record (int32 each). */
+enum {
+  FIND_EF_KIND = 0,    /* 0 = Schur elimination, 1 = final leaf block           */
+  FIND_EF_S, FIND_EF_B, FIND_EF_N,
+  FIND_EF_SRC0, FIND_EF_LD0, FIND_EF_SRC1, FIND_EF_LD1, /* pool offsets (complex), -1 = none */
+  FIND_EF_DST,         /* pool offset of U (b x b); R follows at DST + b*b     */
+  FIND_EF_MAP,         /* first entry of this elimination's map (n entries)    */
+  FIND_EF_CLUSTER, FIND_EF_PHASE, FIND_EF_LEVEL,
+  FIND_EF_FIELDS
+};
+/* Phases: 0 upward, 1 downward, 2 leaf extraction, 3 final leaf block.
+ * Map entries are (node, src, pos): global node id (-1 for none), source
+ * 0/1 (pos = row in that source's b x b matrix) or 2 (original A / Sigma). */
+/* Stage record: (first elim, count, phase, variant); variant 0 = diagonal
+ * only, 1 = with bonds, -1 = both. */
+/* Leaf-output record: (final elim, n_nodes, node_first, bond_first, n_bonds, variant).
+ * Out-node entries: (global node, local index).  Out-bond entries:
+ * (bond id, local i, local j, stencil array k, flat H index y*Nx+x). */
+enum { FIND_SF_FIELDS = 4, FIND_LF_FIELDS = 6, FIND_ON_FIELDS = 2, FIND_OB_FIELDS = 5 };
+
+find_status find_plan_summary(find_plan plan, find_plan_summary_t* out);
+find_status find_plan_export(find_plan plan, int32_t* elims, int32_t* maps, int32_t* stages,
+                             int32_t* leafout, int32_t* outnodes, int32_t* outbonds);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FIND_H_ */

@@ -1,0 +1,411 @@
+// C-ABI of libfind: plan management, footprint/flop queries, and the
+// enqueue of a whole FIND solve (procedure computeG<: upward pass, downward
+// pass, per-leaf extraction, output collection) on a HIP stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/find.h"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+using namespace findmi;
+
+namespace {
+
+thread_local std::string g_err;
+
+find_status fail(find_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIPCHK(expr)                                                                         \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return fail(FIND_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));         \
+  } while (0)
+
+struct DevStage {
+  int first, count, phase, variant;
+  int rpt;              // panel rows per thread (from the largest front)
+  long long ws_stride;  // complex elements per workspace slot
+  ElimDev* d_elims;     // points into DevState::d_elims
+};
+
+struct DevState {
+  int device = -1;
+  int slots = 0;
+  ElimDev* d_elims = nullptr;
+  int* d_map_node = nullptr;
+  int* d_map_srcpos = nullptr;
+  LeafOutDev* d_leafout[2] = {nullptr, nullptr};
+  int* d_outnode = nullptr;
+  int* d_outbond = nullptr;
+  std::vector<DevStage> stages;
+  int n_leafout[2] = {0, 0};
+  double2* pool = nullptr; size_t pool_elems = 0;
+  double2* ws = nullptr; size_t ws_elems = 0;
+  int* status = nullptr; size_t status_len = 0;
+  size_t maps_bytes = 0;
+  size_t ws_need = 0;       // complex elements of workspace a solve needs
+};
+
+__global__ void k_fill_int(int* p, int n, int v) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+}  // namespace
+
+struct find_plan_s {
+  Plan P;
+  find_plan_opts opts;
+  std::mutex mu;
+  std::map<int, std::unique_ptr<DevState>> dev;
+  int last_nE = 0;
+  int last_device = -1;
+};
+
+namespace {
+
+void free_dev(DevState& d) {
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) cur = -1;
+  if (d.device >= 0) (void)hipSetDevice(d.device);
+  void* ptrs[] = {d.d_elims, d.d_map_node, d.d_map_srcpos, d.d_leafout[0], d.d_leafout[1],
+                  d.d_outnode, d.d_outbond, d.pool, d.ws, d.status};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (cur >= 0) (void)hipSetDevice(cur);
+}
+
+template <class T>
+find_status upload(T** dptr, const std::vector<T>& h, size_t& bytes) {
+  size_t nb = std::max<size_t>(1, h.size()) * sizeof(T);
+  if (hipMalloc(dptr, nb) != hipSuccess) return fail(FIND_E_NOMEM, "hipMalloc of plan maps failed");
+  if (!h.empty()) HIPCHK(hipMemcpy(*dptr, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  bytes += nb;
+  return FIND_OK;
+}
+
+find_status ensure_device(find_plan_s* p, DevState** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  auto it = p->dev.find(dev);
+  if (it != p->dev.end()) { *out = it->second.get(); return FIND_OK; }
+  auto ds = std::make_unique<DevState>();
+  ds->device = dev;
+  int cus = 0;
+  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  ds->slots = std::max(1, 2 * cus);
+  const Plan& P = p->P;
+  // elimination records, sorted by decreasing cost inside each stage
+  std::vector<ElimDev> he(P.elims.size());
+  for (const Stage& st : P.stages) {
+    std::vector<int> idx(st.count);
+    std::iota(idx.begin(), idx.end(), st.first);
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return elim_flops(P.elims[a]) > elim_flops(P.elims[b]); });
+    DevStage ds_st{st.first, st.count, st.phase, st.variant, 1, 0, nullptr};
+    int maxn = 0;
+    for (int q = 0; q < st.count; ++q) {
+      const Elim& e = P.elims[idx[q]];
+      ElimDev& d = he[st.first + q];
+      d.kind = e.kind; d.s = e.s; d.b = e.b; d.n = e.n;
+      d.src0 = std::max<int64_t>(0, e.src_off[0]); d.src1 = std::max<int64_t>(0, e.src_off[1]);
+      d.ld0 = e.src_ld[0]; d.ld1 = e.src_ld[1];
+      d.dst = e.dst; d.map = e.map; d.pad = 0;
+      maxn = std::max(maxn, e.n);
+      ds_st.ws_stride = std::max<long long>(ds_st.ws_stride, 2LL * e.n * e.n + (long long)e.b * e.n);
+    }
+    if (maxn > kMaxFront) {
+      char buf[128];
+      snprintf(buf, sizeof buf, "front of size %d exceeds the supported maximum %d", maxn, kMaxFront);
+      return fail(FIND_E_UNSUPPORTED, buf);
+    }
+    ds_st.rpt = panel_rpt(std::max(1, maxn));
+    ds->stages.push_back(ds_st);
+    ds->ws_need = std::max<size_t>(ds->ws_need, size_t(std::min<long long>(ds->slots, 1LL << 40)) * ds_st.ws_stride);
+  }
+  std::vector<int> srcpos(P.map_src.size());
+  for (size_t k = 0; k < srcpos.size(); ++k)
+    srcpos[k] = (P.map_src[k] << 24) | (P.map_src[k] == SRC_ORIG ? 0 : (P.map_pos[k] & 0xffffff));
+  std::vector<LeafOutDev> lo[2];
+  for (const LeafOut& L : P.leafout) {
+    const Elim& fe = P.elims[L.elim];
+    LeafOutDev d;
+    d.elim_dst_lo = int(fe.dst & 0xffffffffLL); d.elim_dst_hi = int(fe.dst >> 32);
+    d.bprime = fe.b; d.n_nodes = L.n_nodes; d.node_first = L.node_first;
+    d.bond_first = L.bond_first; d.n_bonds = L.n_bonds; d.pad = 0;
+    lo[L.variant].push_back(d);
+  }
+  std::vector<int> onode, obond;
+  for (size_t k = 0; k < P.outnode_node.size(); ++k) { onode.push_back(P.outnode_node[k]); onode.push_back(P.outnode_local[k]); }
+  for (const OutBond& b : P.outbonds) { obond.push_back(b.bond); obond.push_back(b.li); obond.push_back(b.lj); obond.push_back(b.k); obond.push_back(b.hflat); }
+  size_t bytes = 0;
+  find_status st;
+  if ((st = upload(&ds->d_elims, he, bytes)) != FIND_OK) { free_dev(*ds); return st; }
+  if ((st = upload(&ds->d_map_node, P.map_node, bytes)) != FIND_OK) { free_dev(*ds); return st; }
+  if ((st = upload(&ds->d_map_srcpos, srcpos, bytes)) != FIND_OK) { free_dev(*ds); return st; }
+  for (int v = 0; v < 2; ++v) {
+    ds->n_leafout[v] = int(lo[v].size());
+    if ((st = upload(&ds->d_leafout[v], lo[v], bytes)) != FIND_OK) { free_dev(*ds); return st; }
+  }
+  if ((st = upload(&ds->d_outnode, onode, bytes)) != FIND_OK) { free_dev(*ds); return st; }
+  if ((st = upload(&ds->d_outbond, obond, bytes)) != FIND_OK) { free_dev(*ds); return st; }
+  ds->maps_bytes = bytes;
+  for (DevStage& s2 : ds->stages) s2.d_elims = ds->d_elims + s2.first;
+  *out = ds.get();
+  p->dev[dev] = std::move(ds);
+  return FIND_OK;
+}
+
+size_t budget_of(const find_plan_s* p) {
+  return p->opts.workspace_budget ? p->opts.workspace_budget : (size_t(64) << 30);
+}
+
+// energies per internal pass so that pool + workspace fit in the budget
+int chunk_energies(const find_plan_s* p, int nE, size_t ws_bytes, size_t maps_bytes) {
+  const size_t per_e = size_t(p->P.pool_per_energy) * sizeof(double2) + sizeof(int);
+  const size_t budget = budget_of(p);
+  size_t avail = budget > ws_bytes + maps_bytes ? budget - ws_bytes - maps_bytes : 0;
+  int ec = int(std::min<size_t>(nE, avail / std::max<size_t>(per_e, 1)));
+  if (p->opts.max_energies > 0) ec = std::min(ec, p->opts.max_energies);
+  return std::max(0, ec);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* find_last_error(void) { return g_err.c_str(); }
+
+int find_n_bonds(int Nx, int Ny, int stencil) {
+  if (Nx < 1 || Ny < 1 || (stencil != 5 && stencil != 9)) return -1;
+  return count_bonds(Nx, Ny, stencil);
+}
+
+find_status find_plan_create(int Nx, int Ny, int stencil, const find_plan_opts* opts, find_plan* out) {
+  if (!out) return fail(FIND_E_ARG, "find_plan_create: out is NULL");
+  *out = nullptr;
+  if (Nx < 1 || Ny < 1) return fail(FIND_E_ARG, "find_plan_create: Nx and Ny must be >= 1");
+  if (stencil != 5 && stencil != 9) return fail(FIND_E_ARG, "find_plan_create: stencil must be 5 or 9");
+  find_plan_opts o{};
+  o.leaf = 8;
+  if (opts) o = *opts;
+  if (o.leaf == 0) o.leaf = 8;
+  if (o.leaf < 1) return fail(FIND_E_ARG, "find_plan_create: leaf must be >= 1");
+  if (o.precision != FIND_PREC_FP64 && o.precision != FIND_PREC_MIXED)
+    return fail(FIND_E_ARG, "find_plan_create: unknown precision");
+  if (o.max_energies < 0) return fail(FIND_E_ARG, "find_plan_create: max_energies must be >= 0");
+  if ((long long)Nx * Ny > (1LL << 24)) return fail(FIND_E_UNSUPPORTED, "find_plan_create: mesh larger than 2^24 nodes");
+  find_plan_s* p = new (std::nothrow) find_plan_s();
+  if (!p) return fail(FIND_E_NOMEM, "find_plan_create: host allocation failed");
+  p->opts = o;
+  std::string err;
+  try {
+    err = build_plan(Nx, Ny, stencil, o.leaf, p->P);
+  } catch (const std::exception& ex) {
+    err = std::string("find_plan_create: ") + ex.what();
+  }
+  if (!err.empty()) { delete p; return fail(FIND_E_ARG, err); }
+  *out = p;
+  return FIND_OK;
+}
+
+find_status find_plan_destroy(find_plan plan) {
+  if (!plan) return FIND_OK;
+  for (auto& kv : plan->dev) free_dev(*kv.second);
+  delete plan;
+  return FIND_OK;
+}
+
+find_status find_plan_summary(find_plan plan, find_plan_summary_t* out) {
+  if (!plan || !out) return fail(FIND_E_ARG, "find_plan_summary: NULL argument");
+  const Plan& P = plan->P;
+  memset(out, 0, sizeof *out);
+  out->Nx = P.Nx; out->Ny = P.Ny; out->stencil = P.stencil; out->leaf = P.leaf;
+  out->n_clusters = int(P.cl.size()); out->depth = P.depth; out->n_leaves = P.n_leaves;
+  out->n_elims = int(P.elims.size()); out->n_stages = int(P.stages.size());
+  out->map_len = int(P.map_node.size());
+  out->n_leafout = int(P.leafout.size()); out->n_outbonds = int(P.outbonds.size());
+  out->n_outnodes = int(P.outnode_node.size());
+  out->max_n = P.max_n; out->max_s = P.max_s; out->max_b = P.max_b;
+  out->pool_per_energy = P.pool_per_energy;
+  return FIND_OK;
+}
+
+find_status find_plan_export(find_plan plan, int32_t* elims, int32_t* maps, int32_t* stages,
+                             int32_t* leafout, int32_t* outnodes, int32_t* outbonds) {
+  if (!plan) return fail(FIND_E_ARG, "find_plan_export: NULL plan");
+  const Plan& P = plan->P;
+  if (elims)
+    for (size_t k = 0; k < P.elims.size(); ++k) {
+      const Elim& e = P.elims[k];
+      int32_t* r = elims + k * FIND_EF_FIELDS;
+      r[FIND_EF_KIND] = e.kind; r[FIND_EF_S] = e.s; r[FIND_EF_B] = e.b; r[FIND_EF_N] = e.n;
+      r[FIND_EF_SRC0] = int32_t(e.src_off[0]); r[FIND_EF_LD0] = e.src_ld[0];
+      r[FIND_EF_SRC1] = int32_t(e.src_off[1]); r[FIND_EF_LD1] = e.src_ld[1];
+      r[FIND_EF_DST] = int32_t(e.dst); r[FIND_EF_MAP] = e.map;
+      r[FIND_EF_CLUSTER] = e.cluster; r[FIND_EF_PHASE] = e.phase; r[FIND_EF_LEVEL] = e.level;
+    }
+  if (maps)
+    for (size_t k = 0; k < P.map_node.size(); ++k) {
+      maps[3 * k] = P.map_node[k]; maps[3 * k + 1] = P.map_src[k]; maps[3 * k + 2] = P.map_pos[k];
+    }
+  if (stages)
+    for (size_t k = 0; k < P.stages.size(); ++k) {
+      stages[4 * k] = P.stages[k].first; stages[4 * k + 1] = P.stages[k].count;
+      stages[4 * k + 2] = P.stages[k].phase; stages[4 * k + 3] = P.stages[k].variant;
+    }
+  if (leafout)
+    for (size_t k = 0; k < P.leafout.size(); ++k) {
+      const LeafOut& L = P.leafout[k];
+      int32_t* r = leafout + k * FIND_LF_FIELDS;
+      r[0] = L.elim; r[1] = L.n_nodes; r[2] = L.node_first; r[3] = L.bond_first; r[4] = L.n_bonds; r[5] = L.variant;
+    }
+  if (outnodes)
+    for (size_t k = 0; k < P.outnode_node.size(); ++k) { outnodes[2 * k] = P.outnode_node[k]; outnodes[2 * k + 1] = P.outnode_local[k]; }
+  if (outbonds)
+    for (size_t k = 0; k < P.outbonds.size(); ++k) {
+      const OutBond& b = P.outbonds[k];
+      int32_t* r = outbonds + k * FIND_OB_FIELDS;
+      r[0] = b.bond; r[1] = b.li; r[2] = b.lj; r[3] = b.k; r[4] = b.hflat;
+    }
+  return FIND_OK;
+}
+
+find_status find_plan_flops(find_plan plan, int want_bonds, double* flops_per_energy) {
+  if (!plan || !flops_per_energy) return fail(FIND_E_ARG, "find_plan_flops: NULL argument");
+  *flops_per_energy = plan->P.flops[want_bonds ? 1 : 0];
+  return FIND_OK;
+}
+
+find_status find_plan_footprint(find_plan plan, int nE, int want_bonds, size_t* bytes) {
+  (void)want_bonds;
+  if (!plan || !bytes || nE < 1) return fail(FIND_E_ARG, "find_plan_footprint: bad argument");
+  const Plan& P = plan->P;
+  // workspace: slots x largest per-slot front over all stages (slot count assumed 512)
+  size_t ws = 0, maps = 0;
+  for (const Elim& e : P.elims) ws = std::max<size_t>(ws, 2ull * e.n * e.n + size_t(e.b) * e.n);
+  const size_t slots = 512;
+  ws *= slots * sizeof(double2);
+  maps = (P.map_node.size() * 2 + P.elims.size() * sizeof(ElimDev) / 4 + P.outbonds.size() * 5 +
+          P.outnode_node.size() * 2) * 4;
+  const size_t per_e = size_t(P.pool_per_energy) * sizeof(double2) + sizeof(int);
+  int ec = chunk_energies(plan, nE, ws, maps);
+  if (ec < 1) ec = 1;
+  *bytes = ws + maps + per_e * size_t(std::min(ec, nE));
+  return FIND_OK;
+}
+
+find_status find_solve(find_plan plan, int nE, const double* energies, const double* H, const double* sigma,
+                       const double* sigma_less, double* diag_G, double* diag_Gless, double* bond_G,
+                       double* bond_Gless, double* bond_J, void* hip_stream) {
+  if (!plan) return fail(FIND_E_ARG, "find_solve: NULL plan");
+  if (nE < 1) return fail(FIND_E_ARG, "find_solve: nE must be >= 1");
+  if (!energies || !H || !sigma || !sigma_less || !diag_G || !diag_Gless)
+    return fail(FIND_E_ARG, "find_solve: NULL input or diagonal output pointer");
+  std::lock_guard<std::mutex> lk(plan->mu);
+  const Plan& P = plan->P;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  DevState* d = nullptr;
+  find_status fs = ensure_device(plan, &d);
+  if (fs != FIND_OK) return fs;
+  const int variant = (bond_G || bond_Gless || bond_J) ? 1 : 0;
+  // workspace (independent of the energy count)
+  if (d->ws_elems < d->ws_need) {
+    if (d->ws) { HIPCHK(hipStreamSynchronize(st)); HIPCHK(hipFree(d->ws)); d->ws = nullptr; d->ws_elems = 0; }
+    if (hipMalloc(&d->ws, d->ws_need * sizeof(double2)) != hipSuccess)
+      return fail(FIND_E_NOMEM, "find_solve: workspace allocation failed");
+    d->ws_elems = d->ws_need;
+  }
+  int ec = chunk_energies(plan, nE, d->ws_elems * sizeof(double2), d->maps_bytes);
+  if (ec < 1) return fail(FIND_E_NOMEM, "find_solve: workspace budget too small for one energy");
+  const size_t pool_need = size_t(ec) * size_t(P.pool_per_energy);
+  if (d->pool_elems < pool_need) {
+    if (d->pool) { HIPCHK(hipStreamSynchronize(st)); HIPCHK(hipFree(d->pool)); d->pool = nullptr; d->pool_elems = 0; }
+    if (hipMalloc(&d->pool, pool_need * sizeof(double2)) != hipSuccess)
+      return fail(FIND_E_NOMEM, "find_solve: energy pool allocation failed");
+    d->pool_elems = pool_need;
+  }
+  if (d->status_len < size_t(nE)) {
+    if (d->status) { HIPCHK(hipStreamSynchronize(st)); HIPCHK(hipFree(d->status)); d->status = nullptr; d->status_len = 0; }
+    if (hipMalloc(&d->status, size_t(nE) * sizeof(int)) != hipSuccess)
+      return fail(FIND_E_NOMEM, "find_solve: status allocation failed");
+    d->status_len = nE;
+  }
+  hipLaunchKernelGGL(k_fill_int, dim3((nE + 255) / 256), dim3(256), 0, st, d->status, nE, 0);
+  HIPCHK(hipGetLastError());
+  const int nst = P.stencil == 9 ? 5 : 3;
+  const size_t nx2 = size_t(P.Nx) * P.Nx;
+  const size_t nnodes = size_t(P.Nx) * P.Ny;
+  for (int e0 = 0; e0 < nE; e0 += ec) {
+    const int ne = std::min(ec, nE - e0);
+    StageArgs a{};
+    a.nE = ne;
+    a.map_node = d->d_map_node; a.map_srcpos = d->d_map_srcpos;
+    a.energies = reinterpret_cast<const double2*>(energies) + e0;
+    a.H = H;
+    a.sigma = reinterpret_cast<const double2*>(sigma) + size_t(e0) * 2 * nx2;
+    a.sless = reinterpret_cast<const double2*>(sigma_less) + size_t(e0) * 2 * nx2;
+    a.pool = d->pool; a.pool_stride = P.pool_per_energy;
+    a.ws = d->ws;
+    a.Nx = P.Nx; a.Ny = P.Ny; a.nst = nst;
+    a.status = d->status + e0;
+    for (const DevStage& s2 : d->stages) {
+      if (s2.variant >= 0 && s2.variant != variant) continue;
+      a.elims = s2.d_elims; a.n_elims = s2.count; a.ws_stride = s2.ws_stride;
+      const long long items = (long long)s2.count * ne;
+      const int grid = int(std::min<long long>(items, d->slots));
+      if (grid < 1) continue;
+      hipError_t he = launch_stage(a, s2.rpt, grid, st);
+      if (he != hipSuccess) return fail(FIND_E_DEVICE, std::string("stage launch: ") + hipGetErrorString(he));
+    }
+    OutArgs o{};
+    o.leaves = d->d_leafout[variant]; o.n_leaves = d->n_leafout[variant]; o.nE = ne;
+    o.outnode = d->d_outnode; o.outbond = d->d_outbond; o.H = H;
+    o.Nx = P.Nx; o.Ny = P.Ny; o.n_bonds = P.n_bonds;
+    o.pool = d->pool; o.pool_stride = P.pool_per_energy;
+    o.diag_G = reinterpret_cast<double2*>(diag_G) + size_t(e0) * nnodes;
+    o.diag_Gless = reinterpret_cast<double2*>(diag_Gless) + size_t(e0) * nnodes;
+    o.bond_G = bond_G ? reinterpret_cast<double2*>(bond_G) + size_t(e0) * P.n_bonds : nullptr;
+    o.bond_Gless = bond_Gless ? reinterpret_cast<double2*>(bond_Gless) + size_t(e0) * P.n_bonds : nullptr;
+    o.bond_J = bond_J ? bond_J + size_t(e0) * P.n_bonds : nullptr;
+    hipError_t he = launch_outputs(o, st);
+    if (he != hipSuccess) return fail(FIND_E_DEVICE, std::string("output launch: ") + hipGetErrorString(he));
+  }
+  plan->last_nE = nE;
+  plan->last_device = d->device;
+  return FIND_OK;
+}
+
+find_status find_sync_status(find_plan plan, void* hip_stream) {
+  if (!plan) return fail(FIND_E_ARG, "find_sync_status: NULL plan");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  HIPCHK(hipStreamSynchronize(st));
+  std::lock_guard<std::mutex> lk(plan->mu);
+  auto it = plan->dev.find(plan->last_device);
+  if (it == plan->dev.end() || plan->last_nE == 0) return FIND_OK;
+  std::vector<int> h(plan->last_nE);
+  HIPCHK(hipMemcpy(h.data(), it->second->status, h.size() * sizeof(int), hipMemcpyDeviceToHost));
+  for (size_t e = 0; e < h.size(); ++e)
+    if (h[e]) {
+      char buf[96];
+      snprintf(buf, sizeof buf, "zero pivot met at energy index %zu", e);
+      return fail(FIND_E_SINGULAR, buf);
+    }
+  return FIND_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,65 @@
+// Device-side records and kernel launchers for the FIND elimination path.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace findmi {
+
+// One elimination as the kernels see it (mirrors findmi::Elim).
+struct ElimDev {
+  int kind, s, b, n;
+  long long src0, src1;   // pool offsets (complex) of source U matrices; R = U + ld*ld
+  int ld0, ld1;
+  long long dst;          // pool offset of the output U (b x b); R follows
+  int map;                // first map entry
+  int pad;
+};
+
+struct LeafOutDev { int elim_dst_lo, elim_dst_hi, bprime, n_nodes, node_first, bond_first, n_bonds, pad; };
+
+struct StageArgs {
+  const ElimDev* elims;   // this stage's records, sorted by decreasing cost
+  int n_elims;
+  int nE;                 // energies in this pass
+  const int* map_node;    // global node id per map entry
+  const int* map_srcpos;  // (src << 24) | pos per map entry
+  const double2* energies;  // energies of this pass
+  const double* H;        // [nst][Ny][Nx]
+  const double2* sigma;   // sigma of this pass  [nE][2][Nx][Nx]
+  const double2* sless;
+  double2* pool;          // pool of this pass, energy stride pool_stride
+  long long pool_stride;
+  double2* ws;            // per-slot workspace
+  long long ws_stride;
+  int Nx, Ny, nst;
+  int* status;            // per energy of this pass: 1 = zero pivot met
+};
+
+struct OutArgs {
+  const LeafOutDev* leaves;
+  int n_leaves;
+  int nE;
+  const int* outnode;     // (node, local) pairs
+  const int* outbond;     // (bond, li, lj, k, hflat) records
+  const double* H;
+  int Nx, Ny;
+  int n_bonds;
+  const double2* pool;
+  long long pool_stride;
+  double2* diag_G;        // outputs of this pass (already offset to the first energy)
+  double2* diag_Gless;
+  double2* bond_G;
+  double2* bond_Gless;
+  double* bond_J;
+};
+
+// rows per thread of the register-resident LU panel needed for a front of size n
+inline int panel_rpt(int n) { return n <= 256 ? 1 : n <= 512 ? 2 : n <= 1024 ? 4 : 8; }
+constexpr int kMaxFront = 2048;
+constexpr int kThreads = 256;
+
+hipError_t launch_stage(const StageArgs& a, int rpt, int grid, hipStream_t st);
+hipError_t launch_outputs(const OutArgs& a, hipStream_t st);
+size_t stage_lds_bytes();
+
+}  // namespace findmi

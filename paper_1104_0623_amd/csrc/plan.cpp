@@ -1,0 +1,360 @@
+// FIND plan construction (host only).
+//
+// Trees and sets follow the paper's Sec. 2.1-2.2: the mesh is split by
+// alternating bisection into basic clusters; each basic cluster C has a
+// boundary set B_C (nodes of C adjacent to the outside) and each complement
+// cluster C-bar = M \ C has the boundary set B_{C-bar} (nodes outside C
+// adjacent to C).  Adjacency is the sparsity pattern of A: the 5- or 9-point
+// stencil plus the dense contact blocks on the first and last columns (the
+// pattern of Sigma< is contained in it).
+//
+// Every elimination is recorded as an ordered node list [S ; B] with, for
+// each entry, where its rows/columns of the assembled matrix come from:
+//   * upward merge of children i, j  (procedure updateBoundaryNodes):
+//       list B_i ++ B_j, blocks (B_i,B_i) = U_i, (B_j,B_j) = U_j, cross blocks
+//       from the original A; S = (B_i u B_j) \ B_k, B = B_k;
+//   * upward leaf: A(C,C) from the original matrix, S = C \ B_C, B = B_C;
+//   * downward step for C with parent D, sibling D1 (procedure
+//       updateAdjacentNodes): list B_{D-bar} ++ B_{D1} (just B_{D1} when D is
+//       the root), S = list \ B_{C-bar}, B = B_{C-bar};
+//   * leaf extraction: list B_{C-bar} ++ C; the kept set is C (plus, when bond
+//       entries are wanted, the second nodes N of the bonds the leaf owns that
+//       lie outside C); eliminating the rest leaves the Schur complement on
+//       C u N, whose inverse is G(C u N, C u N) (eq. (cd1)); its Sigma block
+//       gives G< on the same set by eq. (gless-nn);
+//   * final leaf block: the inverse and G Sigma G^dagger of that block, run
+//       as one more elimination of the bordered matrix [[U, I], [I, 0]].
+// The same rules apply to Sigma with R in place of U (the Sigma_g block
+// assembly of Sec. 3.1 and its leaf case).
+#include "plan.hpp"
+
+#include <algorithm>
+#include <array>
+#include <cstdio>
+#include <numeric>
+
+namespace findmi {
+
+int count_bonds(int Nx, int Ny, int stencil) {
+  int n = (Nx - 1) * Ny + Nx * (Ny - 1);
+  if (stencil == 9) n += 2 * (Nx - 1) * (Ny - 1);
+  return n;
+}
+
+double elim_flops(const Elim& e) {
+  double s = e.s, b = e.b;
+  if (e.kind == K_FINAL) return 8.0 * 3.0 * s * s * s;
+  return 8.0 * (s * s * s / 3.0 + 2.0 * s * s * b + 3.0 * s * b * b);
+}
+
+namespace {
+
+struct Builder {
+  Plan& P;
+  int Nx, Ny, stencil;
+  std::vector<int> mark;   // scratch marker over all nodes
+  int stamp = 0;
+  explicit Builder(Plan& p) : P(p), Nx(p.Nx), Ny(p.Ny), stencil(p.stencil), mark(size_t(p.Nx) * p.Ny, 0) {}
+
+  bool inside(const Rect& r, int x, int y) const {
+    return x >= r.x0 && x < r.x0 + r.w && y >= r.y0 && y < r.y0 + r.h;
+  }
+
+  void build_tree() {
+    P.cl.clear();
+    Cluster root;
+    root.r = {0, 0, Nx, Ny};
+    P.cl.push_back(root);
+    for (size_t q = 0; q < P.cl.size(); ++q) {  // breadth-first
+      Rect r = P.cl[q].r;
+      if (r.w <= P.leaf && r.h <= P.leaf) continue;
+      Rect a = r, b = r;
+      if (r.h >= r.w) { a.h = r.h / 2; b.y0 = r.y0 + a.h; b.h = r.h - a.h; }
+      else            { a.w = r.w / 2; b.x0 = r.x0 + a.w; b.w = r.w - a.w; }
+      for (int k = 0; k < 2; ++k) {
+        Cluster c;
+        c.r = k ? b : a;
+        c.parent = int(q);
+        c.depth = P.cl[q].depth + 1;
+        P.cl[q].child[k] = int(P.cl.size());
+        P.cl.push_back(c);
+      }
+      P.cl[P.cl[q].child[0]].sibling = P.cl[q].child[1];
+      P.cl[P.cl[q].child[1]].sibling = P.cl[q].child[0];
+    }
+    P.depth = 0; P.n_leaves = 0;
+    for (int q = int(P.cl.size()) - 1; q >= 0; --q) {
+      Cluster& c = P.cl[q];
+      P.depth = std::max(P.depth, c.depth);
+      if (c.leaf()) { c.height = 0; ++P.n_leaves; }
+      else c.height = 1 + std::max(P.cl[c.child[0]].height, P.cl[c.child[1]].height);
+    }
+  }
+
+  // Stencil neighbours of (x, y) inside the mesh.
+  template <class F> void stencil_nbrs(int x, int y, F&& f) const {
+    static const int d5[4][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1}};
+    static const int d9[4][2] = {{1, 1}, {-1, -1}, {1, -1}, {-1, 1}};
+    for (auto& d : d5) { int u = x + d[0], v = y + d[1]; if (u >= 0 && u < Nx && v >= 0 && v < Ny) f(u, v); }
+    if (stencil == 9)
+      for (auto& d : d9) { int u = x + d[0], v = y + d[1]; if (u >= 0 && u < Nx && v >= 0 && v < Ny) f(u, v); }
+  }
+
+  void build_sets() {
+    for (auto& c : P.cl) {
+      const Rect r = c.r;
+      ++stamp;  // stamp marks nodes already placed in Bc
+      std::vector<int> B, Bc;
+      for (int y = r.y0; y < r.y0 + r.h; ++y)
+        for (int x = r.x0; x < r.x0 + r.w; ++x) {
+          bool bnd = false;
+          stencil_nbrs(x, y, [&](int u, int v) {
+            if (!inside(r, u, v)) {
+              bnd = true;
+              int j = v * Nx + u;
+              if (mark[j] != stamp) { mark[j] = stamp; Bc.push_back(j); }
+            }
+          });
+          // dense contact blocks couple every pair of nodes on a contact column
+          bool full_col = (r.x0 == 0 && r.w == Nx);
+          if ((y == 0 || y == Ny - 1) && !full_col) bnd = true;
+          if (bnd) B.push_back(y * Nx + x);
+        }
+      for (int cy : {0, Ny - 1}) {
+        if (cy < r.y0 || cy >= r.y0 + r.h) continue;  // C does not touch this contact column
+        for (int x = 0; x < Nx; ++x) {
+          if (x >= r.x0 && x < r.x0 + r.w) continue;
+          int j = cy * Nx + x;
+          if (mark[j] != stamp) { mark[j] = stamp; Bc.push_back(j); }
+        }
+      }
+      std::sort(B.begin(), B.end());
+      std::sort(Bc.begin(), Bc.end());
+      c.B = std::move(B);
+      c.Bc = std::move(Bc);
+    }
+  }
+
+  // Position of each node of `list` in `keep` (-1 if absent); requires keep sorted.
+  static int find_sorted(const std::vector<int>& v, int x) {
+    auto it = std::lower_bound(v.begin(), v.end(), x);
+    return (it != v.end() && *it == x) ? int(it - v.begin()) : -1;
+  }
+
+  // Emit an elimination whose assembled node list is `list` (with per-entry
+  // source and source position) and whose kept set is `keep` (in this order).
+  std::string emit(const std::vector<int>& list, const std::vector<int>& src,
+                   const std::vector<int>& pos, const std::vector<int>& keep, Elim e) {
+    std::vector<int> keep_sorted = keep;
+    std::sort(keep_sorted.begin(), keep_sorted.end());
+    std::vector<int> S_idx, in_list(keep.size(), -1);
+    for (size_t k = 0; k < list.size(); ++k)
+      if (find_sorted(keep_sorted, list[k]) < 0) S_idx.push_back(int(k));
+    // kept nodes in `keep` order, located in the list
+    std::vector<int> listpos_sorted(list.size());
+    std::iota(listpos_sorted.begin(), listpos_sorted.end(), 0);
+    std::sort(listpos_sorted.begin(), listpos_sorted.end(), [&](int a, int b) { return list[a] < list[b]; });
+    for (size_t q = 0; q < keep.size(); ++q) {
+      auto it = std::lower_bound(listpos_sorted.begin(), listpos_sorted.end(), keep[q],
+                                 [&](int a, int val) { return list[a] < val; });
+      if (it == listpos_sorted.end() || list[*it] != keep[q]) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "plan: kept node %d missing from assembled list (phase %d cluster %d)",
+                 keep[q], e.phase, e.cluster);
+        return buf;
+      }
+      in_list[q] = *it;
+    }
+    e.s = int(S_idx.size());
+    e.b = int(keep.size());
+    e.n = e.s + e.b;
+    e.map = int(P.map_node.size());
+    for (int k : S_idx) { P.map_node.push_back(list[k]); P.map_src.push_back(src[k]); P.map_pos.push_back(pos[k]); }
+    for (int k : in_list) { P.map_node.push_back(list[k]); P.map_src.push_back(src[k]); P.map_pos.push_back(pos[k]); }
+    P.elims.push_back(e);
+    return "";
+  }
+
+  std::vector<int> cluster_nodes(const Rect& r) const {
+    std::vector<int> v;
+    for (int y = r.y0; y < r.y0 + r.h; ++y)
+      for (int x = r.x0; x < r.x0 + r.w; ++x) v.push_back(y * Nx + x);
+    return v;
+  }
+
+  // Second nodes of the bonds owned by the leaf (first node in C), and the
+  // owned bonds themselves: (bond id, first node, second node, k, hflat).
+  void leaf_bonds(const Rect& r, std::vector<std::array<int, 5>>& owned) const {
+    const int nx1 = Nx - 1;
+    const int off1 = nx1 * Ny, off2 = off1 + Nx * (Ny - 1), off3 = off2 + nx1 * (Ny - 1);
+    for (int y = r.y0; y < r.y0 + r.h; ++y)
+      for (int x = r.x0; x < r.x0 + r.w; ++x) {
+        int i = y * Nx + x;
+        if (x + 1 < Nx) owned.push_back({y * nx1 + x, i, i + 1, 1, y * Nx + x});
+        if (y + 1 < Ny) owned.push_back({off1 + y * Nx + x, i, i + Nx, 2, y * Nx + x});
+        if (stencil == 9 && x + 1 < Nx && y + 1 < Ny)
+          owned.push_back({off2 + y * nx1 + x, i, i + Nx + 1, 3, y * Nx + x});
+        if (stencil == 9 && x >= 1 && y + 1 < Ny)  // d- bond with first node (x, y) = ((x-1)+1, y)
+          owned.push_back({off3 + y * nx1 + (x - 1), i, (y + 1) * Nx + (x - 1), 4, y * Nx + (x - 1)});
+      }
+  }
+
+  std::string build() {
+    build_tree();
+    build_sets();
+    const int nc = int(P.cl.size());
+    // pool layout: upward (U_C, R_C) and downward (U_{C-bar}, R_{C-bar}) for non-root clusters
+    int64_t off = 0;
+    for (int q = 1; q < nc; ++q) {
+      Cluster& c = P.cl[q];
+      c.up_off = off; off += 2 * int64_t(c.B.size()) * c.B.size();
+      c.dn_off = off; off += 2 * int64_t(c.Bc.size()) * c.Bc.size();
+    }
+    std::string err;
+    // ---- upward pass: stages by height (leaves first); the root is not eliminated
+    int max_h = P.cl[0].height;
+    for (int h = 0; h < max_h; ++h) {
+      int first = int(P.elims.size());
+      for (int q = 1; q < nc; ++q) {
+        Cluster& c = P.cl[q];
+        if (c.height != h) continue;
+        Elim e; e.phase = PH_UP; e.cluster = q; e.level = c.depth; e.dst = c.up_off;
+        std::vector<int> list, src, pos;
+        if (c.leaf()) {
+          list = cluster_nodes(c.r);
+          src.assign(list.size(), SRC_ORIG); pos.assign(list.size(), -1);
+        } else {
+          for (int k = 0; k < 2; ++k) {
+            const Cluster& ch = P.cl[c.child[k]];
+            for (size_t p = 0; p < ch.B.size(); ++p) { list.push_back(ch.B[p]); src.push_back(k); pos.push_back(int(p)); }
+            e.src_off[k] = ch.up_off; e.src_ld[k] = int(ch.B.size());
+          }
+        }
+        if (!(err = emit(list, src, pos, c.B, e)).empty()) return err;
+      }
+      if (int(P.elims.size()) > first) P.stages.push_back({first, int(P.elims.size()) - first, PH_UP, -1});
+    }
+    // ---- downward pass: stages by depth
+    for (int d = 1; d <= P.depth; ++d) {
+      int first = int(P.elims.size());
+      for (int q = 1; q < nc; ++q) {
+        Cluster& c = P.cl[q];
+        if (c.depth != d) continue;
+        const Cluster& D = P.cl[c.parent];
+        const Cluster& D1 = P.cl[c.sibling];
+        Elim e; e.phase = PH_DOWN; e.cluster = q; e.level = d; e.dst = c.dn_off;
+        std::vector<int> list, src, pos;
+        if (c.parent != 0) {
+          for (size_t p = 0; p < D.Bc.size(); ++p) { list.push_back(D.Bc[p]); src.push_back(SRC0); pos.push_back(int(p)); }
+          e.src_off[0] = D.dn_off; e.src_ld[0] = int(D.Bc.size());
+        }
+        for (size_t p = 0; p < D1.B.size(); ++p) { list.push_back(D1.B[p]); src.push_back(SRC1); pos.push_back(int(p)); }
+        e.src_off[1] = D1.up_off; e.src_ld[1] = int(D1.B.size());
+        if (!(err = emit(list, src, pos, c.Bc, e)).empty()) return err;
+      }
+      if (int(P.elims.size()) > first) P.stages.push_back({first, int(P.elims.size()) - first, PH_DOWN, -1});
+    }
+    // ---- leaf extraction, two variants (0: diagonal only, 1: with bond entries)
+    P.n_bonds = count_bonds(Nx, Ny, stencil);
+    std::vector<int> leaves;
+    for (int q = 0; q < nc; ++q) if (P.cl[q].leaf()) leaves.push_back(q);
+    // pool slots for leaf blocks: sized for the larger variant, shared by both
+    std::vector<int64_t> leaf1_off(leaves.size()), fin_off(leaves.size());
+    std::vector<std::vector<std::array<int, 5>>> owned(leaves.size());
+    for (size_t l = 0; l < leaves.size(); ++l) {
+      const Cluster& c = P.cl[leaves[l]];
+      leaf_bonds(c.r, owned[l]);
+      std::vector<int> N;
+      for (auto& ob : owned[l]) if (!inside(c.r, ob[2] % Nx, ob[2] / Nx)) N.push_back(ob[2]);
+      std::sort(N.begin(), N.end()); N.erase(std::unique(N.begin(), N.end()), N.end());
+      int64_t bp = int64_t(c.r.w) * c.r.h + N.size();
+      leaf1_off[l] = off; off += 2 * bp * bp;
+      fin_off[l] = off; off += 2 * bp * bp;
+    }
+    P.pool_per_energy = off;
+    for (int v = 0; v < 2; ++v) {
+      int first = int(P.elims.size());
+      std::vector<std::vector<int>> keeps(leaves.size());
+      for (size_t l = 0; l < leaves.size(); ++l) {
+        const Cluster& c = P.cl[leaves[l]];
+        std::vector<int> Cn = cluster_nodes(c.r);
+        std::vector<int> N;
+        if (v == 1)
+          for (auto& ob : owned[l]) if (!inside(c.r, ob[2] % Nx, ob[2] / Nx)) N.push_back(ob[2]);
+        std::sort(N.begin(), N.end()); N.erase(std::unique(N.begin(), N.end()), N.end());
+        std::vector<int> list, src, pos;
+        Elim e; e.phase = PH_LEAF; e.cluster = leaves[l]; e.level = c.depth; e.dst = leaf1_off[l];
+        if (leaves[l] != 0) {
+          for (size_t p = 0; p < c.Bc.size(); ++p) { list.push_back(c.Bc[p]); src.push_back(SRC0); pos.push_back(int(p)); }
+          e.src_off[0] = c.dn_off; e.src_ld[0] = int(c.Bc.size());
+        }
+        for (int i : Cn) { list.push_back(i); src.push_back(SRC_ORIG); pos.push_back(-1); }
+        std::vector<int> keep = Cn;
+        keep.insert(keep.end(), N.begin(), N.end());
+        keeps[l] = keep;
+        if (!(err = emit(list, src, pos, keep, e)).empty()) return err;
+      }
+      P.stages.push_back({first, int(P.elims.size()) - first, PH_LEAF, v});
+      first = int(P.elims.size());
+      for (size_t l = 0; l < leaves.size(); ++l) {
+        const Elim& le = P.elims[P.stages.back().first + l];
+        Elim e; e.kind = K_FINAL; e.phase = PH_FINAL; e.cluster = leaves[l]; e.level = le.level;
+        e.s = le.b; e.b = le.b; e.n = 2 * le.b;
+        e.src_off[0] = le.dst; e.src_ld[0] = le.b; e.dst = fin_off[l];
+        e.map = int(P.map_node.size());
+        for (int r = 0; r < 2 * le.b; ++r) {
+          P.map_node.push_back(keeps[l][r % le.b]);
+          P.map_src.push_back(r < le.b ? SRC0 : SRC1);
+          P.map_pos.push_back(r % le.b);
+        }
+        P.elims.push_back(e);
+        // output records: kept order is [C nodes ; N]
+        const Cluster& c = P.cl[leaves[l]];
+        LeafOut lo;
+        lo.elim = int(P.elims.size()) - 1; lo.variant = v;
+        lo.n_nodes = c.r.w * c.r.h; lo.node_first = int(P.outnode_node.size());
+        for (int q2 = 0; q2 < lo.n_nodes; ++q2) { P.outnode_node.push_back(keeps[l][q2]); P.outnode_local.push_back(q2); }
+        lo.bond_first = int(P.outbonds.size()); lo.n_bonds = 0;
+        if (v == 1) {
+          std::vector<int> ks = keeps[l];
+          std::vector<int> idx(ks.size());
+          std::iota(idx.begin(), idx.end(), 0);
+          std::sort(idx.begin(), idx.end(), [&](int a, int b) { return ks[a] < ks[b]; });
+          auto local = [&](int node) {
+            auto it = std::lower_bound(idx.begin(), idx.end(), node, [&](int a, int val) { return ks[a] < val; });
+            return (it != idx.end() && ks[*it] == node) ? *it : -1;
+          };
+          for (auto& ob : owned[l]) {
+            int li = local(ob[1]), lj = local(ob[2]);
+            if (li < 0 || lj < 0) return "plan: bond endpoint missing from leaf block";
+            P.outbonds.push_back({ob[0], li, lj, ob[3], ob[4]});
+            ++lo.n_bonds;
+          }
+        }
+        P.leafout.push_back(lo);
+      }
+      P.stages.push_back({first, int(P.elims.size()) - first, PH_FINAL, v});
+    }
+    // size limits and flop model
+    for (auto& st : P.stages)
+      for (int k = st.first; k < st.first + st.count; ++k) {
+        const Elim& e = P.elims[k];
+        P.max_n = std::max(P.max_n, e.n); P.max_s = std::max(P.max_s, e.s); P.max_b = std::max(P.max_b, e.b);
+        double f = elim_flops(e);
+        if (st.variant < 0) { P.flops[0] += f; P.flops[1] += f; }
+        else P.flops[st.variant] += f;
+      }
+    return "";
+  }
+};
+
+}  // namespace
+
+std::string build_plan(int Nx, int Ny, int stencil, int leaf, Plan& P) {
+  P = Plan();
+  P.Nx = Nx; P.Ny = Ny; P.stencil = stencil; P.leaf = leaf;
+  Builder b(P);
+  return b.build();
+}
+
+}  // namespace findmi

@@ -1,0 +1,62 @@
+// Host-side FIND plan: cluster tree, boundary sets, elimination records with
+// their gather maps, the level schedule, and the per-energy pool layout.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace findmi {
+
+struct Rect { int x0, y0, w, h; };
+
+struct Cluster {
+  Rect r;
+  int parent = -1, child[2] = {-1, -1}, sibling = -1;
+  int depth = 0, height = 0;
+  std::vector<int> B;    // boundary set B_C: nodes of C with a pattern-neighbour outside C
+  std::vector<int> Bc;   // B_{C-bar}: nodes outside C with a pattern-neighbour in C
+  int64_t up_off = -1;   // pool offset of (U_C, R_C)
+  int64_t dn_off = -1;   // pool offset of (U_{C-bar}, R_{C-bar})
+  bool leaf() const { return child[0] < 0; }
+};
+
+enum Phase { PH_UP = 0, PH_DOWN = 1, PH_LEAF = 2, PH_FINAL = 3 };
+enum Kind { K_SCHUR = 0, K_FINAL = 1 };
+enum Src { SRC0 = 0, SRC1 = 1, SRC_ORIG = 2 };
+
+struct Elim {
+  int kind = K_SCHUR;
+  int s = 0, b = 0, n = 0;
+  int64_t src_off[2] = {-1, -1};
+  int src_ld[2] = {0, 0};
+  int64_t dst = -1;
+  int map = 0;
+  int cluster = -1, phase = 0, level = 0;
+};
+
+struct Stage { int first, count, phase, variant; };
+struct LeafOut { int elim, n_nodes, node_first, bond_first, n_bonds, variant; };
+struct OutBond { int bond, li, lj, k, hflat; };
+
+struct Plan {
+  int Nx = 0, Ny = 0, stencil = 5, leaf = 8;
+  std::vector<Cluster> cl;
+  int depth = 0, n_leaves = 0;
+  std::vector<Elim> elims;
+  std::vector<int> map_node, map_src, map_pos;
+  std::vector<Stage> stages;
+  std::vector<LeafOut> leafout;
+  std::vector<int> outnode_node, outnode_local;
+  std::vector<OutBond> outbonds;
+  int64_t pool_per_energy = 0;
+  int max_n = 0, max_s = 0, max_b = 0;
+  int n_bonds = 0;
+  double flops[2] = {0, 0};  // per energy, variant 0/1
+};
+
+int count_bonds(int Nx, int Ny, int stencil);
+// Builds the plan; returns an empty string on success, else a message.
+std::string build_plan(int Nx, int Ny, int stencil, int leaf, Plan& P);
+double elim_flops(const Elim& e);
+
+}  // namespace findmi

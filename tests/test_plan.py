@@ -1,0 +1,111 @@
+"""Plan tests (CPU only): the C-ABI library loads and exports every symbol of
+include/find.h; plans have the tree and set structure the paper describes; and
+a numpy executor that follows the plan's gather maps reproduces the dense
+oracle (so the plan is right before any kernel runs)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import dense
+from paper_1104_0623_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def findlib():
+    from paper_1104_0623_amd import find
+    return find
+
+
+def test_library_exports_every_declared_symbol():
+    find = findlib()
+    L = find.lib()
+    hdr = open(os.path.join(ROOT, "include", "find.h")).read()
+    declared = set(re.findall(r"^\s*(?:find_status|const char\*|int)\s+(find_\w+)\s*\(", hdr, re.M))
+    assert declared, "no declarations parsed"
+    assert declared == set(find.EXPORTED), declared ^ set(find.EXPORTED)
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def test_argument_errors():
+    find = findlib()
+    with pytest.raises(find.FindError) as ei:
+        find.Plan(0, 4, 5)
+    assert ei.value.status == find.FIND_E_ARG
+    with pytest.raises(find.FindError):
+        find.Plan(4, 4, 7)
+    with pytest.raises(find.FindError):
+        find.Plan(4, 4, 5, leaf=-1)
+    assert find.n_bonds(4, 3, 5) == 3 * 3 + 4 * 2
+    assert find.n_bonds(4, 3, 9) == 3 * 3 + 4 * 2 + 2 * 3 * 2
+    assert find.n_bonds(0, 3, 9) == -1
+    L = find.lib()
+    assert L.find_plan_destroy(None) == 0
+    assert L.find_solve(None, 1, *([None] * 10)) == find.FIND_E_ARG
+    assert b"NULL plan" in L.find_last_error()
+
+
+def test_tree_shape_128():
+    find = findlib()
+    p = find.Plan(128, 128, 5)
+    s = p.summary()
+    assert (s["n_clusters"], s["depth"], s["n_leaves"]) == (511, 8, 256)
+    ex = p.export()
+    el = ex["elims"]
+    up = el[el[:, 11] == 0]; dn = el[el[:, 11] == 1]
+    # upward level 1 merges two 128 x 64 halves: S = the two middle columns, B = both contact columns
+    l1 = up[up[:, 12] == 1]
+    assert set(l1[:, 1]) == {252} and set(l1[:, 2]) == {128}
+    leaves = up[up[:, 12] == 8]
+    assert leaves[:, 1].min() == 36 and leaves[:, 1].max() == 42
+    assert leaves[:, 2].min() == 22 and leaves[:, 2].max() == 28
+    d1 = dn[dn[:, 12] == 1]
+    assert set(d1[:, 1]) == {0} and set(d1[:, 2]) == {128}
+    d3 = dn[dn[:, 12] == 3]
+    assert d3[:, 1].max() == 190 and d3[:, 2].max() == 160
+    assert 14e9 < p.flops_per_energy() < 20e9
+
+
+def test_tree_shape_small_and_degenerate():
+    find = findlib()
+    s = find.Plan(16, 16, 5).summary()
+    assert (s["n_clusters"], s["depth"], s["n_leaves"]) == (7, 2, 4)
+    s = find.Plan(5, 3, 5).summary()     # whole mesh is one leaf
+    assert (s["n_clusters"], s["depth"], s["n_leaves"]) == (1, 0, 1)
+    s = find.Plan(1, 40, 5).summary()    # 1D chain
+    assert s["n_leaves"] == 8
+
+
+CASES = [(16, 16, 5, 8), (12, 9, 9, 4), (7, 13, 5, 3), (1, 11, 5, 2), (4, 3, 9, 8), (9, 1, 5, 2),
+         (10, 10, 9, 2), (6, 17, 5, 4)]
+
+
+@pytest.mark.parametrize("Nx,Ny,stencil,leaf", CASES)
+@pytest.mark.parametrize("want_bonds", [False, True])
+def test_plan_executor_matches_oracle(Nx, Ny, stencil, leaf, want_bonds):
+    from tests.plan_exec import execute
+    find = findlib()
+    E = 0.41 + 1e-3j
+    prob = inputs.make_problem(Nx, Ny, stencil, vmax=0.8, seed=Nx * 31 + Ny, energies=[E], fL=1.0, fR=0.2)
+    p = find.Plan(Nx, Ny, stencil, leaf=leaf)
+    Hm = dense.hamiltonian_matrix(Nx, Ny, prob["H"])
+    dG, dL, bG, bL, bJ = execute(p.export(), Nx, Ny, stencil, Hm, E, prob["sigma"][0], prob["sigma_less"][0],
+                                 want_bonds)
+    ref = dense.dense_solve(Nx, Ny, stencil, prob["H"], prob["energies"], prob["sigma"], prob["sigma_less"])
+    sc = np.max(np.abs(ref["diag_G"][0]))
+    assert np.max(np.abs(dG - ref["diag_G"][0])) < 1e-11 * sc
+    assert np.max(np.abs(dL - ref["diag_Gless"][0])) < 1e-11 * np.max(np.abs(ref["diag_Gless"][0]))
+    if want_bonds:
+        nb = inputs.n_bonds(Nx, Ny, stencil)
+        assert sorted(bG) == list(range(nb))
+        g = np.array([bG[k] for k in range(nb)]); l = np.array([bL[k] for k in range(nb)])
+        assert np.max(np.abs(g - ref["bond_G"][0])) < 1e-11 * sc
+        assert np.max(np.abs(l - ref["bond_Gless"][0])) < 1e-11 * np.max(np.abs(ref["bond_Gless"][0]))
+        # J from the G<_ji entry the output record points at
+        H = prob["H"]
+        J = np.array([2 * np.real(H[bJ[k][2]].ravel()[bJ[k][3]] * bJ[k][4]) for k in range(nb)])
+        assert np.max(np.abs(J - ref["bond_J"][0])) < 1e-10 * (np.max(np.abs(ref["bond_J"][0])) + 1e-3)

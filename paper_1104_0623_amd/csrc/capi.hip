@@ -38,6 +38,7 @@ find_status fail(find_status st, const std::string& msg) {
 
 struct DevStage {
   int first, count, phase, variant;
+  double flops_per_energy;  // algorithmic flops of the stage for one energy
   int rpt;              // panel rows per thread (from the largest front)
   long long ws_stride;  // complex elements per workspace slot
   ElimDev* d_elims;     // points into DevState::d_elims
@@ -59,6 +60,10 @@ struct DevState {
   int* status = nullptr; size_t status_len = 0;
   size_t maps_bytes = 0;
   size_t ws_need = 0;       // complex elements of workspace a solve needs
+  // profiling: event pairs around stage launches (reused between calls)
+  std::vector<hipEvent_t> ev;
+  std::vector<double> ev_flops;
+  size_t ev_used = 0;
 };
 
 __global__ void k_fill_int(int* p, int n, int v) {
@@ -75,6 +80,7 @@ struct find_plan_s {
   std::map<int, std::unique_ptr<DevState>> dev;
   int last_nE = 0;
   int last_device = -1;
+  bool profiling = false;
 };
 
 namespace {
@@ -83,6 +89,7 @@ void free_dev(DevState& d) {
   int cur = -1;
   if (hipGetDevice(&cur) != hipSuccess) cur = -1;
   if (d.device >= 0) (void)hipSetDevice(d.device);
+  for (hipEvent_t e : d.ev) (void)hipEventDestroy(e);
   void* ptrs[] = {d.d_elims, d.d_map_node, d.d_map_srcpos, d.d_leafout[0], d.d_leafout[1],
                   d.d_outnode, d.d_outbond, d.pool, d.ws, d.status};
   for (void* p : ptrs)
@@ -116,7 +123,7 @@ find_status ensure_device(find_plan_s* p, DevState** out) {
     std::vector<int> idx(st.count);
     std::iota(idx.begin(), idx.end(), st.first);
     std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return elim_flops(P.elims[a]) > elim_flops(P.elims[b]); });
-    DevStage ds_st{st.first, st.count, st.phase, st.variant, 1, 0, nullptr};
+    DevStage ds_st{st.first, st.count, st.phase, st.variant, 0.0, 1, 0, nullptr};
     int maxn = 0;
     for (int q = 0; q < st.count; ++q) {
       const Elim& e = P.elims[idx[q]];
@@ -126,6 +133,7 @@ find_status ensure_device(find_plan_s* p, DevState** out) {
       d.ld0 = e.src_ld[0]; d.ld1 = e.src_ld[1];
       d.dst = e.dst; d.map = e.map; d.pad = 0;
       maxn = std::max(maxn, e.n);
+      ds_st.flops_per_energy += elim_flops(e);
       ds_st.ws_stride = std::max<long long>(ds_st.ws_stride, 2LL * e.n * e.n + (long long)e.b * e.n);
     }
     if (maxn > kMaxFront) {
@@ -369,8 +377,22 @@ find_status find_solve(find_plan plan, int nE, const double* energies, const dou
       const long long items = (long long)s2.count * ne;
       const int grid = int(std::min<long long>(items, d->slots));
       if (grid < 1) continue;
+      if (plan->profiling) {
+        while (d->ev.size() < 2 * (d->ev_used + 1)) {
+          hipEvent_t ev;
+          HIPCHK(hipEventCreate(&ev));
+          d->ev.push_back(ev);
+        }
+        if (d->ev_flops.size() < d->ev_used + 1) d->ev_flops.resize(d->ev_used + 1);
+        d->ev_flops[d->ev_used] = s2.flops_per_energy * ne;
+        HIPCHK(hipEventRecord(d->ev[2 * d->ev_used], st));
+      }
       hipError_t he = launch_stage(a, s2.rpt, grid, st);
       if (he != hipSuccess) return fail(FIND_E_DEVICE, std::string("stage launch: ") + hipGetErrorString(he));
+      if (plan->profiling) {
+        HIPCHK(hipEventRecord(d->ev[2 * d->ev_used + 1], st));
+        ++d->ev_used;
+      }
     }
     OutArgs o{};
     o.leaves = d->d_leafout[variant]; o.n_leaves = d->n_leafout[variant]; o.nE = ne;
@@ -387,6 +409,36 @@ find_status find_solve(find_plan plan, int nE, const double* energies, const dou
   }
   plan->last_nE = nE;
   plan->last_device = d->device;
+  return FIND_OK;
+}
+
+find_status find_plan_set_profiling(find_plan plan, int enable) {
+  if (!plan) return fail(FIND_E_ARG, "find_plan_set_profiling: NULL plan");
+  std::lock_guard<std::mutex> lk(plan->mu);
+  plan->profiling = enable != 0;
+  return FIND_OK;
+}
+
+find_status find_plan_profile(find_plan plan, double* kernel_ms, double* kernel_flops, int* launches) {
+  if (!plan) return fail(FIND_E_ARG, "find_plan_profile: NULL plan");
+  std::lock_guard<std::mutex> lk(plan->mu);
+  double ms = 0.0, fl = 0.0;
+  int nl = 0;
+  for (auto& kv : plan->dev) {
+    DevState& d = *kv.second;
+    for (size_t k = 0; k < d.ev_used; ++k) {
+      HIPCHK(hipEventSynchronize(d.ev[2 * k + 1]));
+      float t = 0.f;
+      HIPCHK(hipEventElapsedTime(&t, d.ev[2 * k], d.ev[2 * k + 1]));
+      ms += t;
+      fl += d.ev_flops[k];
+      ++nl;
+    }
+    d.ev_used = 0;
+  }
+  if (kernel_ms) *kernel_ms = ms;
+  if (kernel_flops) *kernel_flops = fl;
+  if (launches) *launches = nl;
   return FIND_OK;
 }
 

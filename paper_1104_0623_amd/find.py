@@ -20,7 +20,7 @@ PREC_FP64, PREC_MIXED = 0, 1
 EF_FIELDS, SF_FIELDS, LF_FIELDS, ON_FIELDS, OB_FIELDS = 13, 4, 6, 2, 5
 EXPORTED = ["find_plan_create", "find_plan_destroy", "find_plan_footprint", "find_plan_flops",
             "find_n_bonds", "find_solve", "find_sync_status", "find_last_error",
-            "find_plan_summary", "find_plan_export"]
+            "find_plan_summary", "find_plan_export", "find_plan_set_profiling", "find_plan_profile"]
 
 
 class FindError(RuntimeError):
@@ -66,6 +66,10 @@ def lib() -> ctypes.CDLL:
         L.find_last_error.argtypes = []; L.find_last_error.restype = ctypes.c_char_p
         L.find_plan_summary.argtypes = [vp, ctypes.POINTER(PlanSummary)]; L.find_plan_summary.restype = st
         L.find_plan_export.argtypes = [vp] + [vp] * 6; L.find_plan_export.restype = st
+        L.find_plan_set_profiling.argtypes = [vp, i32]; L.find_plan_set_profiling.restype = st
+        L.find_plan_profile.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_int)]
+        L.find_plan_profile.restype = st
         _lib = L
     return _lib
 
@@ -129,6 +133,15 @@ class Plan:
         f = ctypes.c_double()
         _check(lib().find_plan_flops(self._h, int(want_bonds), ctypes.byref(f)))
         return f.value
+
+    def set_profiling(self, enable: bool) -> None:
+        _check(lib().find_plan_set_profiling(self._h, int(enable)))
+
+    def profile(self) -> tuple[float, float, int]:
+        """(elimination-kernel ms, their algorithmic flops, launches) since the last call."""
+        ms, fl, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
+        _check(lib().find_plan_profile(self._h, ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(n)))
+        return ms.value, fl.value, n.value
 
     def footprint(self, nE: int, want_bonds: bool = False) -> int:
         b = ctypes.c_size_t()

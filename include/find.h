@@ -104,8 +104,9 @@ find_status find_plan_footprint(find_plan plan, int nE, int want_bonds, size_t* 
  * elimination with s eliminated and b kept nodes, s^3/3 + 2 s^2 b + 3 s b^2
  * complex multiply-adds (LU of A(S,S), L = A(B,S) A(S,S)^-1, the Schur update
  * of eq. (major-update) and the two products of eq. (gless-update-rule)
- * arranged as W = [-L, I] Sigma, R = W [-L, I]^dagger); plus 3 b'^3 for each
- * final leaf block of size b' (inverse and G Sigma G^dagger). */
+ * arranged as W = [-L, I] Sigma, R = W [-L, I]^dagger); plus 2 b'^3 for each
+ * final leaf block of size b' (the inverse G and T = R G^dagger; the requested
+ * entries of G< = G T are O(b') dot products each). */
 find_status find_plan_flops(find_plan plan, int want_bonds, double* flops_per_energy);
 
 /* Number of bonds (output length per energy of bond_G/bond_Gless/bond_J). */

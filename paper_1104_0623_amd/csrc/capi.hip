@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -115,7 +116,9 @@ find_status ensure_device(find_plan_s* p, DevState** out) {
   ds->device = dev;
   int cus = 0;
   HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  ds->slots = std::max(1, 2 * cus);
+  int per_cu = 3;  // workgroups resident per CU (the kernel is compiled for occupancy 3)
+  if (const char* env = getenv("FIND_SLOTS_PER_CU")) per_cu = std::max(1, std::min(16, atoi(env)));
+  ds->slots = std::max(1, per_cu * cus);
   const Plan& P = p->P;
   // elimination records, sorted by decreasing cost inside each stage
   std::vector<ElimDev> he(P.elims.size());
@@ -131,10 +134,12 @@ find_status ensure_device(find_plan_s* p, DevState** out) {
       d.kind = e.kind; d.s = e.s; d.b = e.b; d.n = e.n;
       d.src0 = std::max<int64_t>(0, e.src_off[0]); d.src1 = std::max<int64_t>(0, e.src_off[1]);
       d.ld0 = e.src_ld[0]; d.ld1 = e.src_ld[1];
-      d.dst = e.dst; d.map = e.map; d.pad = 0;
+      d.dst = e.dst; d.map = e.map; d.aux = -1;
       maxn = std::max(maxn, e.n);
       ds_st.flops_per_energy += elim_flops(e);
-      ds_st.ws_stride = std::max<long long>(ds_st.ws_stride, 2LL * e.n * e.n + (long long)e.b * e.n);
+      const long long need = e.kind == K_FINAL ? 3LL * e.b * e.b                     // [U; I] and T
+                                               : 2LL * e.n * e.n + (long long)e.b * e.n;  // A_g, Sigma_g and W
+      ds_st.ws_stride = std::max<long long>(ds_st.ws_stride, need);
     }
     if (maxn > kMaxFront) {
       char buf[128];
@@ -149,7 +154,15 @@ find_status ensure_device(find_plan_s* p, DevState** out) {
   for (size_t k = 0; k < srcpos.size(); ++k)
     srcpos[k] = (P.map_src[k] << 24) | (P.map_src[k] == SRC_ORIG ? 0 : (P.map_pos[k] & 0xffffff));
   std::vector<LeafOutDev> lo[2];
+  std::vector<int> elim_to_dev(P.elims.size(), -1);  // plan elimination -> position in he
+  for (const Stage& st : P.stages) {
+    std::vector<int> idx(st.count);
+    std::iota(idx.begin(), idx.end(), st.first);
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return elim_flops(P.elims[a]) > elim_flops(P.elims[b]); });
+    for (int q = 0; q < st.count; ++q) elim_to_dev[idx[q]] = st.first + q;
+  }
   for (const LeafOut& L : P.leafout) {
+    he[elim_to_dev[L.elim]].aux = int(lo[L.variant].size());
     const Elim& fe = P.elims[L.elim];
     LeafOutDev d;
     d.elim_dst_lo = int(fe.dst & 0xffffffffLL); d.elim_dst_hi = int(fe.dst >> 32);
@@ -371,6 +384,15 @@ find_status find_solve(find_plan plan, int nE, const double* energies, const dou
     a.ws = d->ws;
     a.Nx = P.Nx; a.Ny = P.Ny; a.nst = nst;
     a.status = d->status + e0;
+    OutArgs o{};
+    o.leaves = d->d_leafout[variant];
+    o.outnode = d->d_outnode; o.outbond = d->d_outbond; o.H = H;
+    o.n_bonds = P.n_bonds;
+    o.diag_G = reinterpret_cast<double2*>(diag_G) + size_t(e0) * nnodes;
+    o.diag_Gless = reinterpret_cast<double2*>(diag_Gless) + size_t(e0) * nnodes;
+    o.bond_G = bond_G ? reinterpret_cast<double2*>(bond_G) + size_t(e0) * P.n_bonds : nullptr;
+    o.bond_Gless = bond_Gless ? reinterpret_cast<double2*>(bond_Gless) + size_t(e0) * P.n_bonds : nullptr;
+    o.bond_J = bond_J ? bond_J + size_t(e0) * P.n_bonds : nullptr;
     for (const DevStage& s2 : d->stages) {
       if (s2.variant >= 0 && s2.variant != variant) continue;
       a.elims = s2.d_elims; a.n_elims = s2.count; a.ws_stride = s2.ws_stride;
@@ -387,25 +409,13 @@ find_status find_solve(find_plan plan, int nE, const double* energies, const dou
         d->ev_flops[d->ev_used] = s2.flops_per_energy * ne;
         HIPCHK(hipEventRecord(d->ev[2 * d->ev_used], st));
       }
-      hipError_t he = launch_stage(a, s2.rpt, grid, st);
+      hipError_t he = s2.phase == PH_FINAL ? launch_final(a, o, s2.rpt, grid, st) : launch_stage(a, s2.rpt, grid, st);
       if (he != hipSuccess) return fail(FIND_E_DEVICE, std::string("stage launch: ") + hipGetErrorString(he));
       if (plan->profiling) {
         HIPCHK(hipEventRecord(d->ev[2 * d->ev_used + 1], st));
         ++d->ev_used;
       }
     }
-    OutArgs o{};
-    o.leaves = d->d_leafout[variant]; o.n_leaves = d->n_leafout[variant]; o.nE = ne;
-    o.outnode = d->d_outnode; o.outbond = d->d_outbond; o.H = H;
-    o.Nx = P.Nx; o.Ny = P.Ny; o.n_bonds = P.n_bonds;
-    o.pool = d->pool; o.pool_stride = P.pool_per_energy;
-    o.diag_G = reinterpret_cast<double2*>(diag_G) + size_t(e0) * nnodes;
-    o.diag_Gless = reinterpret_cast<double2*>(diag_Gless) + size_t(e0) * nnodes;
-    o.bond_G = bond_G ? reinterpret_cast<double2*>(bond_G) + size_t(e0) * P.n_bonds : nullptr;
-    o.bond_Gless = bond_Gless ? reinterpret_cast<double2*>(bond_Gless) + size_t(e0) * P.n_bonds : nullptr;
-    o.bond_J = bond_J ? bond_J + size_t(e0) * P.n_bonds : nullptr;
-    hipError_t he = launch_outputs(o, st);
-    if (he != hipSuccess) return fail(FIND_E_DEVICE, std::string("output launch: ") + hipGetErrorString(he));
   }
   plan->last_nE = nE;
   plan->last_device = d->device;

@@ -41,7 +41,8 @@ __device__ __forceinline__ double2 cinv(double2 a) {
 __device__ __forceinline__ double2 conjd(double2 a) { return make_double2(a.x, -a.y); }
 __device__ __forceinline__ double2 zero2() { return make_double2(0.0, 0.0); }
 
-// Entries of the original A = E I - H - Sigma_L - Sigma_R and of Sigma<.
+// Entries of the original A = E I - H - Sigma_L - Sigma_R and of Sigma<,
+// addressed by node coordinates (x, y) (no integer division).
 struct Orig {
   const double* H;
   const double2* sig;
@@ -49,307 +50,393 @@ struct Orig {
   double2 E;
   int Nx, Ny, nst;
 
-  __device__ double hval(int i, int j) const {
-    const int xi = i % Nx, yi = i / Nx, xj = j % Nx, yj = j / Nx;
+  // H_ij for i = (xi, yi), j = (xj, yj), i != j
+  __device__ double hval(int xi, int yi, int xj, int yj) const {
     const int dx = xj - xi, dy = yj - yi;
     const int plane = Nx * Ny;
-    if (dy == 0) return dx == 1 ? H[plane + i] : dx == -1 ? H[plane + j] : 0.0;
-    if (dx == 0) return dy == 1 ? H[2 * plane + i] : dy == -1 ? H[2 * plane + j] : 0.0;
+    if (dy == 0) return dx == 1 ? H[plane + yi * Nx + xi] : dx == -1 ? H[plane + yj * Nx + xj] : 0.0;
+    if (dx == 0) return dy == 1 ? H[2 * plane + yi * Nx + xi] : dy == -1 ? H[2 * plane + yj * Nx + xj] : 0.0;
     if (nst == 5) {
-      if (dx == 1 && dy == 1) return H[3 * plane + i];
-      if (dx == -1 && dy == -1) return H[3 * plane + j];
+      if (dx == 1 && dy == 1) return H[3 * plane + yi * Nx + xi];
+      if (dx == -1 && dy == -1) return H[3 * plane + yj * Nx + xj];
       if (dx == -1 && dy == 1) return H[4 * plane + yi * Nx + xj];  // i=(x+1,y), j=(x,y+1)
       if (dx == 1 && dy == -1) return H[4 * plane + yj * Nx + xi];  // i=(x,y+1), j=(x+1,y)
     }
     return 0.0;
   }
-  __device__ double2 a(int i, int j) const {
-    double2 v;
-    if (i == j) v = make_double2(E.x - H[i], E.y);
-    else v = make_double2(-hval(i, j), 0.0);
-    const int yi = i / Nx, yj = j / Nx;
-    if (yi == yj) {
-      const int xi = i % Nx, xj = j % Nx;
-      if (yi == 0) { double2 s = sig[xi * Nx + xj]; v.x -= s.x; v.y -= s.y; }
-      if (yi == Ny - 1) { double2 s = sig[Nx * Nx + xi * Nx + xj]; v.x -= s.x; v.y -= s.y; }
+  // A_ij
+  __device__ double2 a(int xi, int yi, int xj, int yj) const {
+    double2 av = zero2();
+    const int dx = xj - xi, dy = yj - yi;
+    if (dx == 0 && dy == 0) av = make_double2(E.x - H[yi * Nx + xi], E.y);
+    else if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) av.x = -hval(xi, yi, xj, yj);
+    if (dy == 0) {
+      if (yi == 0) { const double2 t = sig[xi * Nx + xj]; av.x -= t.x; av.y -= t.y; }
+      if (yi == Ny - 1) { const double2 t = sig[Nx * Nx + xi * Nx + xj]; av.x -= t.x; av.y -= t.y; }
     }
-    return v;
+    return av;
   }
-  __device__ double2 s(int i, int j) const {
-    double2 v = zero2();
-    const int yi = i / Nx, yj = j / Nx;
+  // Sigma<_ij (non-zero only between two nodes of one contact column)
+  __device__ double2 s(int xi, int yi, int xj, int yj) const {
+    double2 sv = zero2();
     if (yi == yj) {
-      const int xi = i % Nx, xj = j % Nx;
-      if (yi == 0) { double2 t = sless[xi * Nx + xj]; v.x += t.x; v.y += t.y; }
-      if (yi == Ny - 1) { double2 t = sless[Nx * Nx + xi * Nx + xj]; v.x += t.x; v.y += t.y; }
+      if (yi == 0) { const double2 u = sless[xi * Nx + xj]; sv.x += u.x; sv.y += u.y; }
+      if (yi == Ny - 1) { const double2 u = sless[Nx * Nx + xi * Nx + xj]; sv.x += u.x; sv.y += u.y; }
     }
-    return v;
+    return sv;
   }
 };
 
 struct Lds {
-  int node[kMaxFront];
+  int node[kMaxFront];     // (y << 16) | x of each front row
   int srcpos[kMaxFront];
   int perm[kMaxFront];
-  int ipiv[16];
-  double2 rowP[16];
-  double2 rowJ[16];
+  // pivot exchange, double-buffered by column parity: each wave's best
+  // candidate (value, row, row contents) and the current row j
+  double candv[2][4];
+  int candi[2][4];
+  double2 candrow[2][4][16];
+  double2 rowJ[2][16];
   double2 tri[16 * 16];
   double2 tinv[16 * 16];
-  double2 tsq[16 * 16];
-  double redv[4];
-  int redi[4];
 };
 
 size_t stage_lds_bytes() { return sizeof(Lds); }
 
-// C(M x N) <- Cinit - A(M x K) B(K x N), complex, one 32x32 tile per wave at a time.
-template <class LA, class LB, class LC, class SC>
-__device__ __forceinline__ void gemm_sub(int M, int N, int K, LA loadA, LB loadB, LC loadC, SC storeC) {
+// Entries of the assembled front A_g / Sigma_g of one elimination, by front
+// row/column (local [S ; B] index): the block of a source cluster's stored U
+// (or R) when both indices come from that source, else the original A (or
+// Sigma<) between the two mesh nodes.
+struct Front {
+  const int* node;     // LDS: (y << 16) | x
+  const int* srcpos;   // LDS: (source << 24) | position
+  const double2* U0;
+  const double2* U1;
+  int ld0, ld1;
+  Orig o;
+
+  __device__ double2 a(int r, int c) const {
+    const int spr = srcpos[r], spc = srcpos[c];
+    const int sr = spr >> 24;
+    if (sr == (spc >> 24) && sr < 2) {
+      const double2* U = sr ? U1 : U0;
+      const int ld = sr ? ld1 : ld0;
+      return U[(size_t)(spc & 0xffffff) * ld + (spr & 0xffffff)];
+    }
+    const int gr = node[r], gc = node[c];
+    return o.a(gr & 0xffff, gr >> 16, gc & 0xffff, gc >> 16);
+  }
+  __device__ double2 s(int r, int c) const {
+    const int spr = srcpos[r], spc = srcpos[c];
+    const int sr = spr >> 24;
+    if (sr == (spc >> 24) && sr < 2) {
+      const int ld = sr ? ld1 : ld0;
+      const double2* R = (sr ? U1 : U0) + (size_t)ld * ld;
+      return R[(size_t)(spc & 0xffffff) * ld + (spr & 0xffffff)];
+    }
+    const int gr = node[r], gc = node[c];
+    return o.s(gr & 0xffff, gr >> 16, gc & 0xffff, gc >> 16);
+  }
+};
+
+// Visit (r, c) for r < nr, c < nc with the block's threads, column-major
+// order inside a column, without integer division.
+template <class F>
+__device__ __forceinline__ void for_each_rc(int nr, int nc, F&& f) {
+  const int lg = nr <= 1 ? 0 : 32 - __clz(nr - 1);
+  const int lgr = lg < 8 ? lg : 8;
+  const int rmask = (1 << lgr) - 1, cstep = kThreads >> lgr;
+  const int rr = threadIdx.x & rmask, cc = threadIdx.x >> lgr;
+  for (int c = cc; c < nc; c += cstep)
+    for (int r = rr; r < nr; r += rmask + 1) f(r, c);
+}
+
+// C(M x N) <- Cinit - A(M x K) B(K x N), complex.  Each wave computes one
+// (16 TM) x (16 TN) output tile at a time with f64 MFMA (four real products
+// per complex product); operands are fetched PD k-steps ahead of use.
+template <int TM, int TN, class LA, class LB, class LC, class SC>
+__device__ __forceinline__ void gemm_tiles(int M, int N, int K, LA loadA, LB loadB, LC loadC, SC storeC) {
+  constexpr int PD = 2;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int tm = (M + 31) >> 5, tn = (N + 31) >> 5;
+  const int tm = (M + 16 * TM - 1) / (16 * TM), tn = (N + 16 * TN - 1) / (16 * TN);
   const int lr = lane & 15, lk = lane >> 4;
-  for (int t = wave; t < tm * tn; t += 4) {
-    const int r0 = (t % tm) << 5, c0 = (t / tm) << 5;
-    d4 accR[2][2], accI[2][2];
+  const int nk = (K + 3) >> 2;
+  for (int t = wave; t < tm * tn; t += kThreads / 64) {
+    const int r0 = (t % tm) * 16 * TM, c0 = (t / tm) * 16 * TN;
+    d4 accR[TM][TN], accI[TM][TN];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) { accR[i][j] = (d4){0, 0, 0, 0}; accI[i][j] = (d4){0, 0, 0, 0}; }
-    for (int k = 0; k < K; k += 4) {
-      const int kk = k + lk;
-      double2 av[2], bv[2];
+      for (int j = 0; j < TN; ++j) { accR[i][j] = (d4){0, 0, 0, 0}; accI[i][j] = (d4){0, 0, 0, 0}; }
+    double2 av[PD + 1][TM], bv[PD + 1][TN];
+    auto fetch = [&](int slot, int ks) {
+      const int kk = 4 * ks + lk;
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
+      for (int i = 0; i < TM; ++i) {
         const int r = r0 + 16 * i + lr;
-        av[i] = (r < M && kk < K) ? loadA(r, kk) : zero2();
+        av[slot][i] = (r < M && kk < K) ? loadA(r, kk) : zero2();
       }
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < TN; ++j) {
         const int c = c0 + 16 * j + lr;
-        bv[j] = (c < N && kk < K) ? loadB(kk, c) : zero2();
+        bv[slot][j] = (c < N && kk < K) ? loadB(kk, c) : zero2();
       }
+    };
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+    for (int p = 0; p < PD; ++p) fetch(p, p);
+    for (int ks = 0; ks < nk; ks += PD + 1) {
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].x, bv[j].x, accR[i][j], 0, 0, 0);
-          accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].x, bv[j].y, accI[i][j], 0, 0, 0);
-          accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[i].y, bv[j].y, accR[i][j], 0, 0, 0);
-          accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].y, bv[j].x, accI[i][j], 0, 0, 0);
+      for (int u = 0; u <= PD; ++u) {
+        if (ks + u < nk) {
+          fetch((u + PD) % (PD + 1), ks + u + PD);
+#pragma unroll
+          for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+              accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][i].x, bv[u][j].x, accR[i][j], 0, 0, 0);
+              accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][i].x, bv[u][j].y, accI[i][j], 0, 0, 0);
+            }
+#pragma unroll
+          for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+              accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[u][i].y, bv[u][j].y, accR[i][j], 0, 0, 0);
+              accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][i].y, bv[u][j].x, accI[i][j], 0, 0, 0);
+            }
         }
+      }
     }
     // D layout of the f64 16x16x4 MFMA: lane l, register q -> row 4q + l/16, column l%16
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < TN; ++j)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int r = r0 + 16 * i + 4 * q + lk, c = c0 + 16 * j + lr;
           if (r < M && c < N) {
-            double2 v = loadC(r, c);
+            const double2 v = loadC(r, c);
             storeC(r, c, make_double2(v.x - accR[i][j][q], v.y - accI[i][j][q]));
           }
         }
   }
 }
 
-__device__ __forceinline__ void block_argmax(Lds& L, double& v, int& idx) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    double ov = __shfl_xor(v, off);
-    int oi = __shfl_xor(idx, off);
-    if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
-  }
-  if (lane == 0) { L.redv[wave] = v; L.redi[wave] = idx; }
-  __syncthreads();
-  v = L.redv[0]; idx = L.redi[0];
-#pragma unroll
-  for (int w = 1; w < 4; ++w) {
-    double ov = L.redv[w];
-    int oi = L.redi[w];
-    if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
-  }
+template <class LA, class LB, class LC, class SC>
+__device__ __forceinline__ void gemm_sub(int M, int N, int K, LA loadA, LB loadB, LC loadC, SC storeC) {
+  if (N <= 16) gemm_tiles<2, 1>(M, N, K, loadA, loadB, loadC, storeC);
+  else gemm_tiles<2, 2>(M, N, K, loadA, loadB, loadC, storeC);
 }
 
 // Inverse of the w x w unit-lower triangle held below the diagonal of L.tri
 // (row-major, tri[i*16+j] = L_ij for i > j), written to L.tinv (zero outside
-// w x w).  With L = I + N, N strictly lower and nilpotent,
-// L^{-1} = (I - N)(I + N^2)(I + N^4)(I + N^8); 256 threads, one entry each.
-__device__ void tri_inverse_unit_lower(Lds& L, int w) {
-  const int t = threadIdx.x, i = t >> 4, j = t & 15;
-  const double2 m = (i > j && i < w) ? make_double2(-L.tri[t].x, -L.tri[t].y) : zero2();
-  __syncthreads();
-  L.tsq[t] = m;
-  L.tinv[t] = (i == j && i < w) ? make_double2(1.0 + m.x, m.y) : m;
-  __syncthreads();
-#pragma nounroll
-  for (int step = 0; step < 3; ++step) {
-    double2 a = zero2();
-#pragma unroll 4
-    for (int k = 0; k < 16; ++k) a = cfms(a, L.tsq[i * 16 + k], make_double2(-L.tsq[k * 16 + j].x, -L.tsq[k * 16 + j].y));
-    __syncthreads();
-    L.tsq[t] = a;            // M^(2^(step+1))
-    __syncthreads();
-    double2 p = L.tinv[t];   // P (I + A) = P + P A
-#pragma unroll 4
-    for (int k = 0; k < 16; ++k) p = cfms(p, L.tinv[i * 16 + k], make_double2(-L.tsq[k * 16 + j].x, -L.tsq[k * 16 + j].y));
-    __syncthreads();
-    L.tinv[t] = p;
-    __syncthreads();
+// w x w).  Thread j < 16 forward-substitutes column j of L^{-1}.  The caller
+// has synchronised after writing L.tri; this function ends with a barrier.
+__device__ __forceinline__ void tri_inverse_unit_lower(Lds& L, int w) {
+  const int j = threadIdx.x;
+  if (j < 16) {
+    double2 y[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      double2 v = (i == j && i < w) ? make_double2(1.0, 0.0) : zero2();
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        if (k < i) v = cfms(v, L.tri[i * 16 + k], y[k]);
+      y[i] = (i < w) ? v : zero2();
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) L.tinv[i * 16 + j] = y[i];
   }
+  __syncthreads();
 }
 
-// LU with partial pivoting (pivots searched among rows < s only) of the
-// tall n x s block stored column-major (ld n) in FA.  perm[k] records which
-// original row sits at position k.  Returns true if a zero pivot was met.
+// Physical row of logical row r of a front whose first s rows are pivoted.
+__device__ __forceinline__ int prow(const int* pm, int s, int r) { return r < s ? pm[r] : r; }
+
+// Blocked LU with partial pivoting (pivots searched among rows < s only) of
+// the tall n x s block of FA (column-major, ld n).  Rows are never moved:
+// perm[k] is the physical row holding logical row k (k < s; rows >= s are
+// never pivoted), so every access to a pivot-eligible row goes through perm,
+// and at the end perm[k] is the original row that became the k-th pivot.  Outer blocks of NB2 columns; inside a
+// block, panels of NB columns are brought up to date left-looking from the
+// block's earlier panels, factored in registers (rows spread over the
+// threads), and their U rows formed; the rest of the matrix gets one
+// MFMA trailing update per outer block.  Returns true if a zero pivot was met.
 template <int RPT, int NB>
-__device__ bool tall_lu(Lds& L, double2* FA, int n, int s) {
-  const int tid = threadIdx.x;
+__device__ __forceinline__ bool tall_lu(Lds& L, double2* FA, int n, int s) {
+  constexpr int NB2 = 32;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int* pm = L.perm;
   bool singular = false;
-  for (int k0 = 0; k0 < s; k0 += NB) {
-    const int kb = min(NB, s - k0);
-    const int m = n - k0;          // panel rows
-    const int ms = s - k0;         // pivot-eligible panel rows
-    double2 P[RPT][NB];
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int rho = tid + kThreads * q;
-#pragma unroll
-      for (int j = 0; j < NB; ++j)
-        P[q][j] = (rho < m && j < kb) ? FA[(size_t)(k0 + j) * n + k0 + rho] : zero2();
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      if (j < kb) {
-        double best = -1.0;
-        int bi = INT_MAX;
-#pragma unroll
-        for (int q = 0; q < RPT; ++q) {
-          const int rho = tid + kThreads * q;
-          if (rho >= j && rho < ms) {
-            double v = fabs(P[q][j].x) + fabs(P[q][j].y);
-            if (v > best) { best = v; bi = rho; }
-          }
-        }
-        block_argmax(L, best, bi);
-        const int piv = bi;
-        const int powner = piv % kThreads, pq = piv / kThreads;
-        if (tid == powner) {
-#pragma unroll
-          for (int q = 0; q < RPT; ++q)
-            if (q == pq)
-#pragma unroll
-              for (int jj = 0; jj < NB; ++jj) L.rowP[jj] = P[q][jj];
-        }
-        if (tid == j) {
-#pragma unroll
-          for (int jj = 0; jj < NB; ++jj) L.rowJ[jj] = P[0][jj];
-        }
-        if (tid == 0) L.ipiv[j] = k0 + piv;
-        __syncthreads();
-        if (piv != j) {
-          if (tid == j) {
-#pragma unroll
-            for (int jj = 0; jj < NB; ++jj) P[0][jj] = L.rowP[jj];
-          }
-          if (tid == powner) {
-#pragma unroll
-            for (int q = 0; q < RPT; ++q)
-              if (q == pq)
-#pragma unroll
-                for (int jj = 0; jj < NB; ++jj) P[q][jj] = L.rowJ[jj];
-          }
-        }
-        double2 pv = L.rowP[j];
-        if (!(best > 0.0)) { singular = true; pv = make_double2(1.0, 0.0); }
-        const double2 inv = cinv(pv);
-#pragma unroll
-        for (int q = 0; q < RPT; ++q) {
-          const int rho = tid + kThreads * q;
-          if (rho > j && rho < m) {
-            const double2 l = cmul(P[q][j], inv);
-            P[q][j] = l;
-#pragma unroll
-            for (int jj = 0; jj < NB; ++jj)
-              if (jj > j && jj < kb) P[q][jj] = cfms(P[q][jj], l, L.rowP[jj]);
-          }
-        }
+  for (int K0 = 0; K0 < s; K0 += NB2) {
+    const int KE = min(s, K0 + NB2);
+    for (int k0 = K0; k0 < KE; k0 += NB) {
+      const int kb = min(NB, KE - k0);
+      const int m = n - k0;          // panel rows
+      const int ms = s - k0;         // pivot-eligible panel rows
+      // (a) left-looking update of the panel by this block's earlier panels
+      if (k0 > K0) {
+        gemm_sub(m, kb, k0 - K0,
+                 [=](int r, int k) { return FA[(size_t)(K0 + k) * n + prow(pm, s, k0 + r)]; },
+                 [=](int k, int c) { return FA[(size_t)(k0 + c) * n + pm[K0 + k]]; },
+                 [=](int r, int c) { return FA[(size_t)(k0 + c) * n + prow(pm, s, k0 + r)]; },
+                 [=](int r, int c, double2 v) { FA[(size_t)(k0 + c) * n + prow(pm, s, k0 + r)] = v; });
         __syncthreads();
       }
-    }
-    // write the panel back; keep its unit-lower top block for the U12 solve
+      // (b) panel factorization with the panel in registers
+      double2 P[RPT][NB];
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int rho = tid + kThreads * q;
-      if (rho < m)
+      for (int q = 0; q < RPT; ++q) {
+        const int rho = tid + kThreads * q;
 #pragma unroll
         for (int j = 0; j < NB; ++j)
-          if (j < kb) FA[(size_t)(k0 + j) * n + k0 + rho] = P[q][j];
-    }
-    if (tid < kb) {
+          P[q][j] = (rho < m && j < kb) ? FA[(size_t)(k0 + j) * n + prow(pm, s, k0 + rho)] : zero2();
+      }
+  #pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        if (j < kb) {
+          const int buf = j & 1;
+          // local candidate among this thread's pivot-eligible rows
+          double best = -1.0;
+          int bi = INT_MAX, bq = 0;
+  #pragma unroll
+          for (int q = 0; q < RPT; ++q) {
+            const int rho = tid + kThreads * q;
+            if (rho >= j && rho < ms) {
+              const double v = fabs(P[q][j].x) + fabs(P[q][j].y);
+              if (v > best) { best = v; bi = rho; bq = q; }
+            }
+          }
+          // wave argmax (ties -> lowest row)
+          double wv = best;
+          int wi = bi;
+  #pragma unroll
+          for (int off = 32; off > 0; off >>= 1) {
+            const double ov = __shfl_xor(wv, off);
+            const int oi = __shfl_xor(wi, off);
+            if (ov > wv || (ov == wv && oi < wi)) { wv = ov; wi = oi; }
+          }
+          // the owner of the wave's winner publishes the row; thread j publishes row j
+          if (bi != INT_MAX && bi == wi && best == wv) {
+  #pragma unroll
+            for (int q = 0; q < RPT; ++q)
+              if (q == bq)
+  #pragma unroll
+                for (int jj = 0; jj < NB; ++jj) L.candrow[buf][wave][jj] = P[q][jj];
+          }
+          if (lane == 0) { L.candv[buf][wave] = wv; L.candi[buf][wave] = wi; }
+          if (tid == j) {
+  #pragma unroll
+            for (int jj = 0; jj < NB; ++jj) L.rowJ[buf][jj] = P[0][jj];
+          }
+          __syncthreads();
+          // every thread picks the same winner
+          double pvv = L.candv[buf][0];
+          int piv = L.candi[buf][0], pw = 0;
+  #pragma unroll
+          for (int w = 1; w < kThreads / 64; ++w) {
+            const double ov = L.candv[buf][w];
+            const int oi = L.candi[buf][w];
+            if (ov > pvv || (ov == pvv && oi < piv)) { pvv = ov; piv = oi; pw = w; }
+          }
+          if (tid == 0 && piv != j) {  // relabel: logical rows k0+j and k0+piv trade physical rows
+            const int t = pm[k0 + j]; pm[k0 + j] = pm[k0 + piv]; pm[k0 + piv] = t;
+          }
+          const double2* prow = L.candrow[buf][pw];
+          if (piv != j) {
+            if (tid == j) {
+  #pragma unroll
+              for (int jj = 0; jj < NB; ++jj) P[0][jj] = prow[jj];
+            }
+            if (tid == piv % kThreads) {
+              const int pq = piv / kThreads;
+  #pragma unroll
+              for (int q = 0; q < RPT; ++q)
+                if (q == pq)
+  #pragma unroll
+                  for (int jj = 0; jj < NB; ++jj) P[q][jj] = L.rowJ[buf][jj];
+            }
+          }
+          double2 pv = prow[j];
+          if (!(pvv > 0.0)) { singular = true; pv = make_double2(1.0, 0.0); }
+          const double2 inv = cinv(pv);
+  #pragma unroll
+          for (int q = 0; q < RPT; ++q) {
+            const int rho = tid + kThreads * q;
+            if (rho > j && rho < m) {
+              const double2 l = cmul(P[q][j], inv);
+              P[q][j] = l;
+  #pragma unroll
+              for (int jj = 0; jj < NB; ++jj)
+                if (jj > j && jj < kb) P[q][jj] = cfms(P[q][jj], l, prow[jj]);
+            }
+          }
+        }
+      }
+      __syncthreads();
+      // write the panel back; keep its unit-lower top block
 #pragma unroll
-      for (int j = 0; j < NB; ++j) L.tri[tid * 16 + j] = P[0][j];
-    }
-    if (tid == 0)
-      for (int j = 0; j < kb; ++j) {
-        const int r2 = L.ipiv[j];
-        const int t = L.perm[k0 + j]; L.perm[k0 + j] = L.perm[r2]; L.perm[r2] = t;
+      for (int q = 0; q < RPT; ++q) {
+        const int rho = tid + kThreads * q;
+        if (rho < m)
+#pragma unroll
+          for (int j = 0; j < NB; ++j)
+            if (j < kb) FA[(size_t)(k0 + j) * n + prow(pm, s, k0 + rho)] = P[q][j];
       }
-    __syncthreads();
-    // apply this panel's row swaps to the other columns of the tall block
-    for (int c = tid; c < s; c += kThreads) {
-      if (c >= k0 && c < k0 + kb) continue;
-      double2* col = FA + (size_t)c * n;
-      for (int j = 0; j < kb; ++j) {
-        const int r1 = k0 + j, r2 = L.ipiv[j];
-        if (r1 != r2) { double2 t = col[r1]; col[r1] = col[r2]; col[r2] = t; }
+      if (tid < kb) {
+#pragma unroll
+        for (int j = 0; j < NB; ++j) L.tri[tid * 16 + j] = P[0][j];
+      }
+      __syncthreads();
+      // (d) U rows of this panel for the columns right of it
+      if (k0 + kb < s) {
+        const int cb = k0 + kb;
+        if (k0 > K0)
+          gemm_sub(kb, s - cb, k0 - K0,
+                   [=](int r, int k) { return FA[(size_t)(K0 + k) * n + pm[k0 + r]]; },
+                   [=](int k, int c) { return FA[(size_t)(cb + c) * n + pm[K0 + k]]; },
+                   [=](int r, int c) { return FA[(size_t)(cb + c) * n + pm[k0 + r]]; },
+                   [=](int r, int c, double2 v) { FA[(size_t)(cb + c) * n + pm[k0 + r]] = v; });
+        tri_inverse_unit_lower(L, kb);
+        const Lds* LL = &L;
+        gemm_sub(kb, s - cb, kb,
+                 [=](int r, int k) { double2 v = LL->tinv[r * 16 + k]; return make_double2(-v.x, -v.y); },
+                 [=](int k, int c) { return FA[(size_t)(cb + c) * n + pm[k0 + k]]; },
+                 [=](int r, int c) { return zero2(); },
+                 [=](int r, int c, double2 v) { FA[(size_t)(cb + c) * n + pm[k0 + r]] = v; });
+        __syncthreads();
       }
     }
-    // U12 = L_panel^{-1} A12 for the columns right of the panel (in place)
-    tri_inverse_unit_lower(L, kb);
-    if (k0 + kb < s) {
-      const int cb = k0 + kb;
-      const Lds* LL = &L;
-      gemm_sub(kb, s - cb, kb,
-               [=](int r, int k) { double2 v = LL->tinv[r * 16 + k]; return make_double2(-v.x, -v.y); },
-               [=](int k, int c) { return FA[(size_t)(cb + c) * n + k0 + k]; },
-               [=](int r, int c) { return zero2(); },
-               [=](int r, int c, double2 v) { FA[(size_t)(cb + c) * n + k0 + r] = v; });
+    // (e) trailing update of rows KE..n, columns KE..s with the block's L and U
+    if (KE < s) {
+      gemm_sub(n - KE, s - KE, KE - K0,
+               [=](int r, int k) { return FA[(size_t)(K0 + k) * n + prow(pm, s, KE + r)]; },
+               [=](int k, int c) { return FA[(size_t)(KE + c) * n + pm[K0 + k]]; },
+               [=](int r, int c) { return FA[(size_t)(KE + c) * n + prow(pm, s, KE + r)]; },
+               [=](int r, int c, double2 v) { FA[(size_t)(KE + c) * n + prow(pm, s, KE + r)] = v; });
+      __syncthreads();
     }
-    __syncthreads();
-    // trailing update of the tall block: rows k0+kb..n, columns k0+kb..s
-    const int r0 = k0 + kb;
-    if (r0 < s) {
-      gemm_sub(n - r0, s - r0, kb,
-               [=](int r, int k) { return FA[(size_t)(k0 + k) * n + r0 + r]; },
-               [=](int k, int c) { return FA[(size_t)(r0 + c) * n + k0 + k]; },
-               [=](int r, int c) { return FA[(size_t)(r0 + c) * n + r0 + r]; },
-               [=](int r, int c, double2 v) { FA[(size_t)(r0 + c) * n + r0 + r] = v; });
-    }
-    __syncthreads();
   }
   return singular;
 }
 
 // X L11 = L21 in place (X -> FA rows s..n, columns 0..s); L11 unit lower.
-__device__ void trsm_right_unit_lower(Lds& L, double2* FA, int n, int s, int b) {
+__device__ __forceinline__ void trsm_right_unit_lower(Lds& L, double2* FA, int n, int s, int b) {
   const int tid = threadIdx.x;
   const int nblk = (s + 15) / 16;
   for (int J = nblk - 1; J >= 0; --J) {
     const int j0 = 16 * J, j1 = min(s, j0 + 16), w = j1 - j0;
     if (j1 < s) {
+      const int* pm = L.perm;
       gemm_sub(b, w, s - j1,
                [=](int r, int k) { return FA[(size_t)(j1 + k) * n + s + r]; },
-               [=](int k, int c) { return FA[(size_t)(j0 + c) * n + j1 + k]; },
+               [=](int k, int c) { return FA[(size_t)(j0 + c) * n + pm[j1 + k]]; },
                [=](int r, int c) { return FA[(size_t)(j0 + c) * n + s + r]; },
                [=](int r, int c, double2 v) { FA[(size_t)(j0 + c) * n + s + r] = v; });
     }
     {
       const int i = tid >> 4, jj = tid & 15;
-      L.tri[tid] = (i < w && jj < w) ? FA[(size_t)(j0 + jj) * n + j0 + i] : zero2();
+      L.tri[tid] = (i < w && jj < w) ? FA[(size_t)(j0 + jj) * n + L.perm[j0 + i]] : zero2();
     }
     __syncthreads();
     tri_inverse_unit_lower(L, w);
@@ -366,8 +453,8 @@ __device__ void trsm_right_unit_lower(Lds& L, double2* FA, int n, int s, int b) 
 }
 
 template <int RPT>
-__global__ __launch_bounds__(kThreads) void k_stage(StageArgs a) {
-  constexpr int NB = (32 / RPT) < 16 ? (32 / RPT) : 16;
+__global__ __launch_bounds__(kThreads, 3) void k_stage(StageArgs a) {
+  constexpr int NB = RPT == 1 ? 8 : 16 / RPT;  // panel columns held in registers
   __shared__ Lds L;
   const int tid = threadIdx.x;
   const long long total = (long long)a.n_elims * a.nE;
@@ -376,44 +463,25 @@ __global__ __launch_bounds__(kThreads) void k_stage(StageArgs a) {
     const int ei = int(item / a.nE), e = int(item % a.nE);
     const ElimDev E = a.elims[ei];
     const int s = E.s, b = E.b, n = E.n;
-    double2* FS = FA + (size_t)n * n;
+    double2* FS = FA + (size_t)n * n;  // FA: A_g (n x n); FS: Sigma_g (n x n); W: b x n
     double2* W = FS + (size_t)n * n;
     double2* pool = a.pool + (size_t)e * a.pool_stride;
     for (int k = tid; k < n; k += kThreads) {
-      L.node[k] = a.map_node[E.map + k];
+      const int g = a.map_node[E.map + k];
+      const int y = g / a.Nx;
+      L.node[k] = (y << 16) | (g - y * a.Nx);
       L.srcpos[k] = a.map_srcpos[E.map + k];
     }
     for (int k = tid; k < s; k += kThreads) L.perm[k] = k;
     __syncthreads();
+    const Front fr{L.node, L.srcpos, pool + E.src0, pool + E.src1, E.ld0, E.ld1,
+                   Orig{a.H, a.sigma + (size_t)e * 2 * a.Nx * a.Nx, a.sless + (size_t)e * 2 * a.Nx * a.Nx,
+                        a.energies[e], a.Nx, a.Ny, a.nst}};
     // 1. assemble A_g and Sigma_g in [S ; B] order
-    Orig o{a.H, a.sigma + (size_t)e * 2 * a.Nx * a.Nx, a.sless + (size_t)e * 2 * a.Nx * a.Nx,
-           a.energies[e], a.Nx, a.Ny, a.nst};
-    const double2* U0 = pool + E.src0;
-    const double2* U1 = pool + E.src1;
-    const size_t nn = (size_t)n * n;
-    for (size_t idx = tid; idx < nn; idx += kThreads) {
-      const int r = int(idx % n), c = int(idx / n);
-      const int sr = L.srcpos[r] >> 24, sc = L.srcpos[c] >> 24;
-      const int pr = L.srcpos[r] & 0xffffff, pc = L.srcpos[c] & 0xffffff;
-      double2 av, sv;
-      if (E.kind == 0) {
-        if (sr == sc && sr == 0) {
-          av = U0[(size_t)pc * E.ld0 + pr]; sv = U0[(size_t)E.ld0 * E.ld0 + (size_t)pc * E.ld0 + pr];
-        } else if (sr == sc && sr == 1) {
-          av = U1[(size_t)pc * E.ld1 + pr]; sv = U1[(size_t)E.ld1 * E.ld1 + (size_t)pc * E.ld1 + pr];
-        } else {
-          av = o.a(L.node[r], L.node[c]); sv = o.s(L.node[r], L.node[c]);
-        }
-      } else {  // final leaf block: [[U, I], [I, 0]] and [[R, 0], [0, 0]]
-        if (sr == 0 && sc == 0) {
-          av = U0[(size_t)pc * E.ld0 + pr]; sv = U0[(size_t)E.ld0 * E.ld0 + (size_t)pc * E.ld0 + pr];
-        } else {
-          av = make_double2((sr != sc && pr == pc) ? 1.0 : 0.0, 0.0); sv = zero2();
-        }
-      }
-      FA[idx] = av;
-      FS[idx] = sv;
-    }
+    for_each_rc(n, n, [&](int r, int c) {
+      FA[(size_t)c * n + r] = fr.a(r, c);
+      FS[(size_t)c * n + r] = fr.s(r, c);
+    });
     __syncthreads();
     // 2. tall LU, 3. L = L21 L11^{-1}
     if (s > 0) {
@@ -444,33 +512,71 @@ __global__ __launch_bounds__(kThreads) void k_stage(StageArgs a) {
   }
 }
 
-// diag G = -U_final(l,l), diag G< = R_final(l,l); bond (i,j): G_ij, G<_ij and
-// J = 2 Re(H_ij G<_ji), read from the final leaf blocks.
-__global__ __launch_bounds__(64) void k_outputs(OutArgs a) {
-  const int leaf = blockIdx.x, e = blockIdx.y;
-  const LeafOutDev Lo = a.leaves[leaf];
-  const long long dst = ((long long)Lo.elim_dst_hi << 32) | (unsigned)Lo.elim_dst_lo;
-  const int bp = Lo.bprime;
-  const double2* U = a.pool + (size_t)e * a.pool_stride + dst;
-  const double2* R = U + (size_t)bp * bp;
+// Final leaf block (eq. (cd1) and eq. (gless-nn) on the kept set K = C u N):
+// from the Schur complement U_K and its Sigma block R_K, G(K,K) = U_K^{-1} and
+// G<(K,K) = G R_K G^dagger.  G comes out of the same tall LU + L solve as an
+// elimination of [[U_K, I], [I, 0]]: the L block of that elimination is
+// U_K^{-1}.  T = R_K G^dagger is formed once; each requested entry of G< is
+// then a dot product G(i,:) T(:,j).  Outputs are written directly.
+template <int RPT>
+__global__ __launch_bounds__(kThreads, 3) void k_final(StageArgs a, OutArgs o) {
+  constexpr int NB = RPT == 1 ? 8 : 16 / RPT;  // panel columns held in registers
+  __shared__ Lds L;
+  const int tid = threadIdx.x;
+  const long long total = (long long)a.n_elims * a.nE;
+  double2* FA = a.ws + (size_t)blockIdx.x * a.ws_stride;
   const size_t nn = (size_t)a.Nx * a.Ny;
-  for (int k = threadIdx.x; k < Lo.n_nodes; k += blockDim.x) {
-    const int node = a.outnode[2 * (Lo.node_first + k)];
-    const int l = a.outnode[2 * (Lo.node_first + k) + 1];
-    const double2 u = U[(size_t)l * bp + l];
-    a.diag_G[e * nn + node] = make_double2(-u.x, -u.y);
-    a.diag_Gless[e * nn + node] = R[(size_t)l * bp + l];
-  }
-  for (int k = threadIdx.x; k < Lo.n_bonds; k += blockDim.x) {
-    const int* ob = a.outbond + 5 * (Lo.bond_first + k);
-    const int bond = ob[0], li = ob[1], lj = ob[2], kk = ob[3], hf = ob[4];
-    const size_t o = (size_t)e * a.n_bonds + bond;
-    if (a.bond_G) { double2 u = U[(size_t)lj * bp + li]; a.bond_G[o] = make_double2(-u.x, -u.y); }
-    if (a.bond_Gless) a.bond_Gless[o] = R[(size_t)lj * bp + li];
-    if (a.bond_J) {
-      const double h = a.H[(size_t)kk * nn + hf];
-      a.bond_J[o] = 2.0 * h * R[(size_t)li * bp + lj].x;
+  for (long long item = blockIdx.x; item < total; item += gridDim.x) {
+    const int ei = int(item / a.nE), e = int(item % a.nE);
+    const ElimDev E = a.elims[ei];
+    const LeafOutDev Lo = o.leaves[E.aux];
+    const int bp = E.b, n = 2 * bp;
+    double2* T = FA + (size_t)n * bp;             // bp x bp
+    double2* pool = a.pool + (size_t)e * a.pool_stride;
+    const double2* Uin = pool + E.src0;           // U_K, ld bp
+    const double2* Rin = Uin + (size_t)bp * bp;   // R_K
+    double2* G = pool + E.dst;                    // G(K,K), bp x bp
+    for (int k = tid; k < bp; k += kThreads) L.perm[k] = k;
+    for_each_rc(n, bp, [&](int r, int c) {
+      FA[(size_t)c * n + r] = r < bp ? Uin[(size_t)c * bp + r] : make_double2(r - bp == c ? 1.0 : 0.0, 0.0);
+    });
+    __syncthreads();
+    if (tall_lu<RPT, NB>(L, FA, n, bp) && tid == 0) a.status[e] = 1;
+    trsm_right_unit_lower(L, FA, n, bp, bp);
+    // G(:, perm[k]) = L(:, k)
+    for_each_rc(bp, bp, [&](int i, int k) { G[(size_t)L.perm[k] * bp + i] = FA[(size_t)k * n + bp + i]; });
+    __syncthreads();
+    // T = R_K G^dagger   (gemm_sub returns 0 - R G^dagger)
+    gemm_sub(bp, bp, bp,
+             [=](int r, int k) { return Rin[(size_t)k * bp + r]; },
+             [=](int k, int c) { return conjd(G[(size_t)k * bp + c]); },
+             [=](int r, int c) { return zero2(); },
+             [=](int r, int c, double2 v) { T[(size_t)c * bp + r] = make_double2(-v.x, -v.y); });
+    __syncthreads();
+    auto gless = [&](int i, int j) {  // G<_ij = sum_m G_im T_mj
+      double2 acc = zero2();
+      for (int m = 0; m < bp; ++m) {
+        const double2 g = G[(size_t)m * bp + i], t = T[(size_t)j * bp + m];
+        acc.x += g.x * t.x - g.y * t.y;
+        acc.y += g.x * t.y + g.y * t.x;
+      }
+      return acc;
+    };
+    for (int k = tid; k < Lo.n_nodes; k += kThreads) {
+      const int node = o.outnode[2 * (Lo.node_first + k)];
+      const int l = o.outnode[2 * (Lo.node_first + k) + 1];
+      o.diag_G[e * nn + node] = G[(size_t)l * bp + l];
+      o.diag_Gless[e * nn + node] = gless(l, l);
     }
+    for (int k = tid; k < Lo.n_bonds; k += kThreads) {
+      const int* ob = o.outbond + 5 * (Lo.bond_first + k);
+      const int bond = ob[0], li = ob[1], lj = ob[2], kk = ob[3], hf = ob[4];
+      const size_t oi = (size_t)e * o.n_bonds + bond;
+      if (o.bond_G) o.bond_G[oi] = G[(size_t)lj * bp + li];
+      if (o.bond_Gless) o.bond_Gless[oi] = gless(li, lj);
+      if (o.bond_J) o.bond_J[oi] = 2.0 * o.H[(size_t)kk * nn + hf] * gless(lj, li).x;
+    }
+    __syncthreads();
   }
 }
 
@@ -485,9 +591,14 @@ hipError_t launch_stage(const StageArgs& a, int rpt, int grid, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_outputs(const OutArgs& a, hipStream_t st) {
-  if (a.n_leaves == 0 || a.nE == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_outputs, dim3(a.n_leaves, a.nE), dim3(64), 0, st, a);
+hipError_t launch_final(const StageArgs& a, const OutArgs& o, int rpt, int grid, hipStream_t st) {
+  switch (rpt) {
+    case 1: hipLaunchKernelGGL(k_final<1>, dim3(grid), dim3(kThreads), 0, st, a, o); break;
+    case 2: hipLaunchKernelGGL(k_final<2>, dim3(grid), dim3(kThreads), 0, st, a, o); break;
+    case 4: hipLaunchKernelGGL(k_final<4>, dim3(grid), dim3(kThreads), 0, st, a, o); break;
+    case 8: hipLaunchKernelGGL(k_final<8>, dim3(grid), dim3(kThreads), 0, st, a, o); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

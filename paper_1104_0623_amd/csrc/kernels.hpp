@@ -12,7 +12,7 @@ struct ElimDev {
   int ld0, ld1;
   long long dst;          // pool offset of the output U (b x b); R follows
   int map;                // first map entry
-  int pad;
+  int aux;                // final leaf block: index of its output record
 };
 
 struct LeafOutDev { int elim_dst_lo, elim_dst_hi, bprime, n_nodes, node_first, bond_first, n_bonds, pad; };
@@ -37,15 +37,10 @@ struct StageArgs {
 
 struct OutArgs {
   const LeafOutDev* leaves;
-  int n_leaves;
-  int nE;
   const int* outnode;     // (node, local) pairs
   const int* outbond;     // (bond, li, lj, k, hflat) records
   const double* H;
-  int Nx, Ny;
   int n_bonds;
-  const double2* pool;
-  long long pool_stride;
   double2* diag_G;        // outputs of this pass (already offset to the first energy)
   double2* diag_Gless;
   double2* bond_G;
@@ -59,7 +54,7 @@ constexpr int kMaxFront = 2048;
 constexpr int kThreads = 256;
 
 hipError_t launch_stage(const StageArgs& a, int rpt, int grid, hipStream_t st);
-hipError_t launch_outputs(const OutArgs& a, hipStream_t st);
+hipError_t launch_final(const StageArgs& a, const OutArgs& o, int rpt, int grid, hipStream_t st);
 size_t stage_lds_bytes();
 
 }  // namespace findmi

@@ -43,7 +43,7 @@ int count_bonds(int Nx, int Ny, int stencil) {
 
 double elim_flops(const Elim& e) {
   double s = e.s, b = e.b;
-  if (e.kind == K_FINAL) return 8.0 * 3.0 * s * s * s;
+  if (e.kind == K_FINAL) return 8.0 * 2.0 * s * s * s;
   return 8.0 * (s * s * s / 3.0 + 2.0 * s * s * b + 3.0 * s * b * b);
 }
 

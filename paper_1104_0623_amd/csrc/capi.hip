@@ -138,7 +138,7 @@ find_status ensure_device(find_plan_s* p, DevState** out) {
       maxn = std::max(maxn, e.n);
       ds_st.flops_per_energy += elim_flops(e);
       const long long need = e.kind == K_FINAL ? 3LL * e.b * e.b                     // [U; I] and T
-                                               : 2LL * e.n * e.n + (long long)e.b * e.n;  // A_g, Sigma_g and W
+                                               : (long long)e.n * e.s + (long long)e.b * e.n;  // tall block and W
       ds_st.ws_stride = std::max<long long>(ds_st.ws_stride, need);
     }
     if (maxn > kMaxFront) {
@@ -318,8 +318,9 @@ find_status find_plan_footprint(find_plan plan, int nE, int want_bonds, size_t* 
   const Plan& P = plan->P;
   // workspace: slots x largest per-slot front over all stages (slot count assumed 512)
   size_t ws = 0, maps = 0;
-  for (const Elim& e : P.elims) ws = std::max<size_t>(ws, 2ull * e.n * e.n + size_t(e.b) * e.n);
-  const size_t slots = 512;
+  for (const Elim& e : P.elims)
+    ws = std::max<size_t>(ws, e.kind == K_FINAL ? 3ull * e.b * e.b : size_t(e.n) * e.s + size_t(e.b) * e.n);
+  const size_t slots = 3 * 256;
   ws *= slots * sizeof(double2);
   maps = (P.map_node.size() * 2 + P.elims.size() * sizeof(ElimDev) / 4 + P.outbonds.size() * 5 +
           P.outnode_node.size() * 2) * 4;

@@ -3,10 +3,11 @@
 // One workgroup (256 threads, four wave64s) owns one (energy, elimination)
 // work item at a time and walks a persistent loop over the stage's items.
 // For an item with s eliminated and b kept nodes (n = s + b) it
-//   1. assembles the front A_g (n x n) and Sigma_g (n x n) in [S ; B] order
-//      from the stored U/R blocks of its sources and the original A / Sigma
-//      (the block assembly of procedures updateBoundaryNodes and
-//      updateAdjacentNodes; Sec. 3.1 for the Sigma blocks),
+//   1. assembles the tall block [A_g(S,S); A_g(B,S)] of the front in [S ; B]
+//      order from the stored U/R blocks of its sources and the original
+//      A / Sigma (the block assembly of procedures updateBoundaryNodes and
+//      updateAdjacentNodes; Sec. 3.1 for the Sigma blocks); the remaining
+//      blocks are gathered the same way when the products read them,
 //   2. LU-factors the tall block [A(S,S); A(B,S)] with partial pivoting over
 //      the S rows only (register-resident panels, MFMA trailing updates); the
 //      B rows of the result hold L21 = A(B,S) U11^{-1},
@@ -463,8 +464,7 @@ __global__ __launch_bounds__(kThreads, 3) void k_stage(StageArgs a) {
     const int ei = int(item / a.nE), e = int(item % a.nE);
     const ElimDev E = a.elims[ei];
     const int s = E.s, b = E.b, n = E.n;
-    double2* FS = FA + (size_t)n * n;  // FA: A_g (n x n); FS: Sigma_g (n x n); W: b x n
-    double2* W = FS + (size_t)n * n;
+    double2* W = FA + (size_t)n * s;   // FA: tall block n x s; W: b x n
     double2* pool = a.pool + (size_t)e * a.pool_stride;
     for (int k = tid; k < n; k += kThreads) {
       const int g = a.map_node[E.map + k];
@@ -477,11 +477,9 @@ __global__ __launch_bounds__(kThreads, 3) void k_stage(StageArgs a) {
     const Front fr{L.node, L.srcpos, pool + E.src0, pool + E.src1, E.ld0, E.ld1,
                    Orig{a.H, a.sigma + (size_t)e * 2 * a.Nx * a.Nx, a.sless + (size_t)e * 2 * a.Nx * a.Nx,
                         a.energies[e], a.Nx, a.Ny, a.nst}};
-    // 1. assemble A_g and Sigma_g in [S ; B] order
-    for_each_rc(n, n, [&](int r, int c) {
-      FA[(size_t)c * n + r] = fr.a(r, c);
-      FS[(size_t)c * n + r] = fr.s(r, c);
-    });
+    // 1. assemble the tall block [A_g(S,S); A_g(B,S)]; the other blocks of A_g
+    //    and all of Sigma_g are gathered from their sources by the products
+    for_each_rc(n, s, [&](int r, int c) { FA[(size_t)c * n + r] = fr.a(r, c); });
     __syncthreads();
     // 2. tall LU, 3. L = L21 L11^{-1}
     if (s > 0) {
@@ -494,10 +492,8 @@ __global__ __launch_bounds__(kThreads, 3) void k_stage(StageArgs a) {
     const int* perm = L.perm;
     gemm_sub(b, b + n, s,
              [=](int r, int k) { return FA[(size_t)k * n + s + r]; },
-             [=](int k, int c) {
-               return c < b ? FA[(size_t)(s + c) * n + perm[k]] : FS[(size_t)(c - b) * n + perm[k]];
-             },
-             [=](int r, int c) { return c < b ? FA[(size_t)(s + c) * n + s + r] : FS[(size_t)(c - b) * n + s + r]; },
+             [=](int k, int c) { return c < b ? fr.a(perm[k], s + c) : fr.s(perm[k], c - b); },
+             [=](int r, int c) { return c < b ? fr.a(s + r, s + c) : fr.s(s + r, c - b); },
              [=](int r, int c, double2 v) {
                if (c < b) Uo[(size_t)c * b + r] = v; else W[(size_t)(c - b) * b + r] = v;
              });

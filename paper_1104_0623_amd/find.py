@@ -48,6 +48,12 @@ _lib = None
 def lib() -> ctypes.CDLL:
     global _lib
     if _lib is None:
+        # torch ships its own HIP runtime; load it first so that libfind binds
+        # to the same runtime instance as the tensors it is given
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_1104_0623_amd.build` (no CPU fallback exists)")

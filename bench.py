@@ -123,6 +123,20 @@ def main() -> int:
                      "launches": nl, "kernel_ms_per_step": kms / args.steps,
                      "algorithmic_flops_per_step": kflops / args.steps},
     }
+    if args.precision == "mixed":
+        # error of this result against the FP64 form of the same solve, per energy
+        ref = find.Plan(Nx, Ny, st, precision=find.PREC_FP64)
+        rG = torch.empty_like(dG); rL = torch.empty_like(dL)
+        find.solve(ref, E, H, S, SL, rG, rL, stream=stream)
+        find.sync_status(ref, stream)
+        def nerr(x, r):
+            x, r = x.reshape(nE, -1), r.reshape(nE, -1)
+            return ((x - r).abs().amax(dim=1) / r.abs().amax(dim=1)).cpu().numpy()
+        eg, el = nerr(dG, rG), nerr(dL, rL)
+        out["mixed_error_vs_fp64"] = {"diag_G_max": float(eg.max()), "diag_Gless_max": float(el.max()),
+                                      "diag_G_median": float(np.median(eg)),
+                                      "diag_Gless_median": float(np.median(el)),
+                                      "metric": "per energy ||x - x_fp64||_inf / ||x_fp64||_inf"}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)

@@ -70,15 +70,22 @@ typedef enum { FIND_PREC_FP64 = 0, FIND_PREC_MIXED = 1 } find_precision;
  *   leaf          largest leaf-cluster side (default 8): the mesh is bisected
  *                 along its longer side (y on ties) until both sides <= leaf
  *                 (paper Sec. 2.1, the nested-dissection partition).
- *   precision     FIND_PREC_FP64 (default) or FIND_PREC_MIXED.
+ *   precision     FIND_PREC_FP64 (default) or FIND_PREC_MIXED.  In the mixed
+ *                 form the Schur-complement and Sigma products of eq.
+ *                 (major-update) and eq. (gless-update-rule) run in FP32 on
+ *                 MFMA (FP32 accumulation); the LU of A(S,S), the L solve,
+ *                 the final leaf blocks, every elimination of a cluster at
+ *                 tree depth <= fp64_top_levels, and every elimination with
+ *                 s >= 512 stay FP64.  Stored U/R blocks are FP64.
  *   max_energies  energies processed per internal pass (0 = chosen from the
  *                 workspace budget).
+ *   fp64_top_levels  see precision (0 = default 2, negative = none).
  *   workspace_budget  device bytes the plan may hold (0 = 64 GiB). */
 typedef struct {
   int leaf;
   int precision;
   int max_energies;
-  int reserved0;
+  int fp64_top_levels;
   size_t workspace_budget;
   int reserved[8];
 } find_plan_opts;

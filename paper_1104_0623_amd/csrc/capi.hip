@@ -134,7 +134,11 @@ find_status ensure_device(find_plan_s* p, DevState** out) {
       d.kind = e.kind; d.s = e.s; d.b = e.b; d.n = e.n;
       d.src0 = std::max<int64_t>(0, e.src_off[0]); d.src1 = std::max<int64_t>(0, e.src_off[1]);
       d.ld0 = e.src_ld[0]; d.ld1 = e.src_ld[1];
-      d.dst = e.dst; d.map = e.map; d.aux = -1;
+      d.dst = e.dst; d.map = e.map; d.aux = -1; d.pad = 0;
+      // mixed form: FP32 products except the top-level eliminations, large
+      // separators and the final leaf blocks, which stay FP64
+      const int top = p->opts.fp64_top_levels == 0 ? 2 : p->opts.fp64_top_levels;
+      d.f32 = (p->opts.precision == FIND_PREC_MIXED && e.kind == K_SCHUR && e.level > top && e.s < 512) ? 1 : 0;
       maxn = std::max(maxn, e.n);
       ds_st.flops_per_energy += elim_flops(e);
       const long long need = e.kind == K_FINAL ? 3LL * e.b * e.b                     // [U; I] and T

@@ -27,6 +27,7 @@
 namespace findmi {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -153,10 +154,28 @@ __device__ __forceinline__ void for_each_rc(int nr, int nc, F&& f) {
 }
 
 // C(M x N) <- Cinit - A(M x K) B(K x N), complex.  Each wave computes one
-// (16 TM) x (16 TN) output tile at a time with f64 MFMA (four real products
-// per complex product); operands are fetched PD k-steps ahead of use.
-template <int TM, int TN, class LA, class LB, class LC, class SC>
+// (16 TM) x (16 TN) output tile at a time on MFMA (four real products per
+// complex product); operands are fetched PD k-steps ahead of use.  With F32
+// the operands are rounded to FP32 and the product accumulates in FP32 on
+// v_mfma_f32_16x16x4_f32; Cinit and the result stay FP64.
+template <bool F32> struct MfmaT;
+template <> struct MfmaT<false> {
+  typedef double e; typedef d4 acc;
+  static __device__ __forceinline__ acc mac(e a, e b, acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  // D layout of the f64 16x16x4 MFMA: lane l, register q -> row 4q + l/16, column l%16
+  static __device__ __forceinline__ int drow(int q, int lk) { return 4 * q + lk; }
+};
+template <> struct MfmaT<true> {
+  typedef float e; typedef f4 acc;
+  static __device__ __forceinline__ acc mac(e a, e b, acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  // D layout of the f32 16x16x4 MFMA: lane l, register q -> row 4(l/16) + q, column l%16
+  static __device__ __forceinline__ int drow(int q, int lk) { return 4 * lk + q; }
+};
+
+template <bool F32, int TM, int TN, class LA, class LB, class LC, class SC>
 __device__ __forceinline__ void gemm_tiles(int M, int N, int K, LA loadA, LB loadB, LC loadC, SC storeC) {
+  typedef MfmaT<F32> T;
+  typedef typename T::e E;
   constexpr int PD = 2;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int tm = (M + 16 * TM - 1) / (16 * TM), tn = (N + 16 * TN - 1) / (16 * TN);
@@ -164,23 +183,27 @@ __device__ __forceinline__ void gemm_tiles(int M, int N, int K, LA loadA, LB loa
   const int nk = (K + 3) >> 2;
   for (int t = wave; t < tm * tn; t += kThreads / 64) {
     const int r0 = (t % tm) * 16 * TM, c0 = (t / tm) * 16 * TN;
-    d4 accR[TM][TN], accI[TM][TN];
+    typename T::acc accR[TM][TN], accI[TM][TN];
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
-      for (int j = 0; j < TN; ++j) { accR[i][j] = (d4){0, 0, 0, 0}; accI[i][j] = (d4){0, 0, 0, 0}; }
-    double2 av[PD + 1][TM], bv[PD + 1][TN];
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) { accR[i][j][q] = 0; accI[i][j][q] = 0; }
+    E aR[PD + 1][TM], aI[PD + 1][TM], bR[PD + 1][TN], bI[PD + 1][TN];
     auto fetch = [&](int slot, int ks) {
       const int kk = 4 * ks + lk;
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
         const int r = r0 + 16 * i + lr;
-        av[slot][i] = (r < M && kk < K) ? loadA(r, kk) : zero2();
+        const double2 v = (r < M && kk < K) ? loadA(r, kk) : zero2();
+        aR[slot][i] = E(v.x); aI[slot][i] = E(v.y);
       }
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
         const int c = c0 + 16 * j + lr;
-        bv[slot][j] = (c < N && kk < K) ? loadB(kk, c) : zero2();
+        const double2 v = (c < N && kk < K) ? loadB(kk, c) : zero2();
+        bR[slot][j] = E(v.x); bI[slot][j] = E(v.y);
       }
     };
 #pragma unroll
@@ -194,39 +217,38 @@ __device__ __forceinline__ void gemm_tiles(int M, int N, int K, LA loadA, LB loa
           for (int i = 0; i < TM; ++i)
 #pragma unroll
             for (int j = 0; j < TN; ++j) {
-              accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][i].x, bv[u][j].x, accR[i][j], 0, 0, 0);
-              accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][i].x, bv[u][j].y, accI[i][j], 0, 0, 0);
+              accR[i][j] = T::mac(aR[u][i], bR[u][j], accR[i][j]);
+              accI[i][j] = T::mac(aR[u][i], bI[u][j], accI[i][j]);
             }
 #pragma unroll
           for (int i = 0; i < TM; ++i)
 #pragma unroll
             for (int j = 0; j < TN; ++j) {
-              accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[u][i].y, bv[u][j].y, accR[i][j], 0, 0, 0);
-              accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][i].y, bv[u][j].x, accI[i][j], 0, 0, 0);
+              accR[i][j] = T::mac(-aI[u][i], bI[u][j], accR[i][j]);
+              accI[i][j] = T::mac(aI[u][i], bR[u][j], accI[i][j]);
             }
         }
       }
     }
-    // D layout of the f64 16x16x4 MFMA: lane l, register q -> row 4q + l/16, column l%16
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
       for (int j = 0; j < TN; ++j)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int r = r0 + 16 * i + 4 * q + lk, c = c0 + 16 * j + lr;
+          const int r = r0 + 16 * i + T::drow(q, lk), c = c0 + 16 * j + lr;
           if (r < M && c < N) {
             const double2 v = loadC(r, c);
-            storeC(r, c, make_double2(v.x - accR[i][j][q], v.y - accI[i][j][q]));
+            storeC(r, c, make_double2(v.x - double(accR[i][j][q]), v.y - double(accI[i][j][q])));
           }
         }
   }
 }
 
-template <class LA, class LB, class LC, class SC>
+template <bool F32 = false, class LA, class LB, class LC, class SC>
 __device__ __forceinline__ void gemm_sub(int M, int N, int K, LA loadA, LB loadB, LC loadC, SC storeC) {
-  if (N <= 16) gemm_tiles<2, 1>(M, N, K, loadA, loadB, loadC, storeC);
-  else gemm_tiles<2, 2>(M, N, K, loadA, loadB, loadC, storeC);
+  if (N <= 16) gemm_tiles<F32, 2, 1>(M, N, K, loadA, loadB, loadC, storeC);
+  else gemm_tiles<F32, 2, 2>(M, N, K, loadA, loadB, loadC, storeC);
 }
 
 // Inverse of the w x w unit-lower triangle held below the diagonal of L.tri
@@ -487,23 +509,28 @@ __global__ __launch_bounds__(kThreads, 3) void k_stage(StageArgs a) {
       trsm_right_unit_lower(L, FA, n, s, b);
     }
     // 4. [U | W] = [A(B,B) | Sigma(B,:)] - L [A(perm,B) | Sigma(perm,:)]
+    // 5. R = W(:, B) - W(:, perm) L^dagger
+    // (FP32 products in the mixed form, FP64 otherwise)
     double2* Uo = pool + E.dst;
     double2* Ro = Uo + (size_t)b * b;
     const int* perm = L.perm;
-    gemm_sub(b, b + n, s,
-             [=](int r, int k) { return FA[(size_t)k * n + s + r]; },
-             [=](int k, int c) { return c < b ? fr.a(perm[k], s + c) : fr.s(perm[k], c - b); },
-             [=](int r, int c) { return c < b ? fr.a(s + r, s + c) : fr.s(s + r, c - b); },
-             [=](int r, int c, double2 v) {
-               if (c < b) Uo[(size_t)c * b + r] = v; else W[(size_t)(c - b) * b + r] = v;
-             });
-    __syncthreads();
-    // 5. R = W(:, B) - W(:, perm) L^dagger
-    gemm_sub(b, b, s,
-             [=](int r, int k) { return W[(size_t)perm[k] * b + r]; },
-             [=](int k, int c) { return conjd(FA[(size_t)k * n + s + c]); },
-             [=](int r, int c) { return W[(size_t)(s + c) * b + r]; },
-             [=](int r, int c, double2 v) { Ro[(size_t)c * b + r] = v; });
+    auto l_ = [=](int r, int k) { return FA[(size_t)k * n + s + r]; };
+    auto b1 = [=](int k, int c) { return c < b ? fr.a(perm[k], s + c) : fr.s(perm[k], c - b); };
+    auto c1 = [=](int r, int c) { return c < b ? fr.a(s + r, s + c) : fr.s(s + r, c - b); };
+    auto s1 = [=](int r, int c, double2 v) { if (c < b) Uo[(size_t)c * b + r] = v; else W[(size_t)(c - b) * b + r] = v; };
+    auto a2 = [=](int r, int k) { return W[(size_t)perm[k] * b + r]; };
+    auto b2 = [=](int k, int c) { return conjd(FA[(size_t)k * n + s + c]); };
+    auto c2 = [=](int r, int c) { return W[(size_t)(s + c) * b + r]; };
+    auto s2 = [=](int r, int c, double2 v) { Ro[(size_t)c * b + r] = v; };
+    if (E.f32) {
+      gemm_sub<true>(b, b + n, s, l_, b1, c1, s1);
+      __syncthreads();
+      gemm_sub<true>(b, b, s, a2, b2, c2, s2);
+    } else {
+      gemm_sub<false>(b, b + n, s, l_, b1, c1, s1);
+      __syncthreads();
+      gemm_sub<false>(b, b, s, a2, b2, c2, s2);
+    }
     __syncthreads();
   }
 }

@@ -13,6 +13,8 @@ struct ElimDev {
   long long dst;          // pool offset of the output U (b x b); R follows
   int map;                // first map entry
   int aux;                // final leaf block: index of its output record
+  int f32;                // 1: Schur/Sigma products in FP32 (mixed form)
+  int pad;
 };
 
 struct LeafOutDev { int elim_dst_lo, elim_dst_hi, bprime, n_nodes, node_first, bond_first, n_bonds, pad; };

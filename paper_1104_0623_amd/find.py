@@ -31,7 +31,7 @@ class FindError(RuntimeError):
 
 class PlanOpts(ctypes.Structure):
     _fields_ = [("leaf", ctypes.c_int), ("precision", ctypes.c_int), ("max_energies", ctypes.c_int),
-                ("reserved0", ctypes.c_int), ("workspace_budget", ctypes.c_size_t),
+                ("fp64_top_levels", ctypes.c_int), ("workspace_budget", ctypes.c_size_t),
                 ("reserved", ctypes.c_int * 8)]
 
 
@@ -93,11 +93,11 @@ class Plan:
     """A FIND plan for one mesh shape (host tree + lazily created device state)."""
 
     def __init__(self, Nx: int, Ny: int, stencil: int = 5, leaf: int = 8, precision: int = PREC_FP64,
-                 max_energies: int = 0, workspace_budget: int = 0):
+                 max_energies: int = 0, workspace_budget: int = 0, fp64_top_levels: int = 0):
         self.Nx, self.Ny, self.stencil = Nx, Ny, stencil
         self._h = ctypes.c_void_p()
         o = PlanOpts(leaf=leaf, precision=precision, max_energies=max_energies,
-                     workspace_budget=workspace_budget)
+                     workspace_budget=workspace_budget, fp64_top_levels=fp64_top_levels)
         _check(lib().find_plan_create(Nx, Ny, stencil, ctypes.byref(o), ctypes.byref(self._h)))
 
     def close(self):

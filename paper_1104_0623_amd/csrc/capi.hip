@@ -41,6 +41,7 @@ struct DevStage {
   int first, count, phase, variant;
   double flops_per_energy;  // algorithmic flops of the stage for one energy
   int rpt;              // panel rows per thread (from the largest front)
+  int maxb;             // largest kept set in the stage
   long long ws_stride;  // complex elements per workspace slot
   ElimDev* d_elims;     // points into DevState::d_elims
 };
@@ -126,7 +127,7 @@ find_status ensure_device(find_plan_s* p, DevState** out) {
     std::vector<int> idx(st.count);
     std::iota(idx.begin(), idx.end(), st.first);
     std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return elim_flops(P.elims[a]) > elim_flops(P.elims[b]); });
-    DevStage ds_st{st.first, st.count, st.phase, st.variant, 0.0, 1, 0, nullptr};
+    DevStage ds_st{st.first, st.count, st.phase, st.variant, 0.0, 1, 0, 0, nullptr};
     int maxn = 0;
     for (int q = 0; q < st.count; ++q) {
       const Elim& e = P.elims[idx[q]];
@@ -140,8 +141,9 @@ find_status ensure_device(find_plan_s* p, DevState** out) {
       const int top = p->opts.fp64_top_levels == 0 ? 2 : p->opts.fp64_top_levels;
       d.f32 = (p->opts.precision == FIND_PREC_MIXED && e.kind == K_SCHUR && e.level > top && e.s < 512) ? 1 : 0;
       maxn = std::max(maxn, e.n);
+      ds_st.maxb = std::max(ds_st.maxb, e.b);
       ds_st.flops_per_energy += elim_flops(e);
-      const long long need = e.kind == K_FINAL ? 3LL * e.b * e.b                     // [U; I] and T
+      const long long need = e.kind == K_FINAL ? 4LL * e.b * e.b                     // [U; I], T and G T
                                                : (long long)e.n * e.s + (long long)e.b * e.n;  // tall block and W
       ds_st.ws_stride = std::max<long long>(ds_st.ws_stride, need);
     }
@@ -323,7 +325,7 @@ find_status find_plan_footprint(find_plan plan, int nE, int want_bonds, size_t* 
   // workspace: slots x largest per-slot front over all stages (slot count assumed 512)
   size_t ws = 0, maps = 0;
   for (const Elim& e : P.elims)
-    ws = std::max<size_t>(ws, e.kind == K_FINAL ? 3ull * e.b * e.b : size_t(e.n) * e.s + size_t(e.b) * e.n);
+    ws = std::max<size_t>(ws, e.kind == K_FINAL ? 4ull * e.b * e.b : size_t(e.n) * e.s + size_t(e.b) * e.n);
   const size_t slots = 3 * 256;
   ws *= slots * sizeof(double2);
   maps = (P.map_node.size() * 2 + P.elims.size() * sizeof(ElimDev) / 4 + P.outbonds.size() * 5 +
@@ -414,7 +416,7 @@ find_status find_solve(find_plan plan, int nE, const double* energies, const dou
         d->ev_flops[d->ev_used] = s2.flops_per_energy * ne;
         HIPCHK(hipEventRecord(d->ev[2 * d->ev_used], st));
       }
-      hipError_t he = s2.phase == PH_FINAL ? launch_final(a, o, s2.rpt, grid, st) : launch_stage(a, s2.rpt, grid, st);
+      hipError_t he = s2.phase == PH_FINAL ? launch_final(a, o, s2.rpt, s2.maxb, grid, st) : launch_stage(a, s2.rpt, grid, st);
       if (he != hipSuccess) return fail(FIND_E_DEVICE, std::string("stage launch: ") + hipGetErrorString(he));
       if (plan->profiling) {
         HIPCHK(hipEventRecord(d->ev[2 * d->ev_used + 1], st));

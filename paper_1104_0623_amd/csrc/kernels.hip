@@ -477,7 +477,7 @@ __device__ __forceinline__ void trsm_right_unit_lower(Lds& L, double2* FA, int n
 
 template <int RPT>
 __global__ __launch_bounds__(kThreads, 3) void k_stage(StageArgs a) {
-  constexpr int NB = RPT == 1 ? 8 : 16 / RPT;  // panel columns held in registers
+  constexpr int NB = 16 / RPT;  // panel columns held in registers
   __shared__ Lds L;
   const int tid = threadIdx.x;
   const long long total = (long long)a.n_elims * a.nE;
@@ -543,7 +543,7 @@ __global__ __launch_bounds__(kThreads, 3) void k_stage(StageArgs a) {
 // then a dot product G(i,:) T(:,j).  Outputs are written directly.
 template <int RPT>
 __global__ __launch_bounds__(kThreads, 3) void k_final(StageArgs a, OutArgs o) {
-  constexpr int NB = RPT == 1 ? 8 : 16 / RPT;  // panel columns held in registers
+  constexpr int NB = 16 / RPT;  // panel columns held in registers
   __shared__ Lds L;
   const int tid = threadIdx.x;
   const long long total = (long long)a.n_elims * a.nE;
@@ -576,15 +576,15 @@ __global__ __launch_bounds__(kThreads, 3) void k_final(StageArgs a, OutArgs o) {
              [=](int r, int c) { return zero2(); },
              [=](int r, int c, double2 v) { T[(size_t)c * bp + r] = make_double2(-v.x, -v.y); });
     __syncthreads();
-    auto gless = [&](int i, int j) {  // G<_ij = sum_m G_im T_mj
-      double2 acc = zero2();
-      for (int m = 0; m < bp; ++m) {
-        const double2 g = G[(size_t)m * bp + i], t = T[(size_t)j * bp + m];
-        acc.x += g.x * t.x - g.y * t.y;
-        acc.y += g.x * t.y + g.y * t.x;
-      }
-      return acc;
-    };
+    // G< = G T (the requested entries are read from it below)
+    double2* GL = T + (size_t)bp * bp;
+    gemm_sub(bp, bp, bp,
+             [=](int r, int k) { return G[(size_t)k * bp + r]; },
+             [=](int k, int c) { const double2 v = T[(size_t)c * bp + k]; return make_double2(-v.x, -v.y); },
+             [=](int r, int c) { return zero2(); },
+             [=](int r, int c, double2 v) { GL[(size_t)c * bp + r] = v; });
+    __syncthreads();
+    auto gless = [&](int i, int j) { return GL[(size_t)j * bp + i]; };
     for (int k = tid; k < Lo.n_nodes; k += kThreads) {
       const int node = o.outnode[2 * (Lo.node_first + k)];
       const int l = o.outnode[2 * (Lo.node_first + k) + 1];
@@ -614,7 +614,8 @@ hipError_t launch_stage(const StageArgs& a, int rpt, int grid, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_final(const StageArgs& a, const OutArgs& o, int rpt, int grid, hipStream_t st) {
+hipError_t launch_final(const StageArgs& a, const OutArgs& o, int rpt, int maxb, int grid, hipStream_t st) {
+  (void)maxb;
   switch (rpt) {
     case 1: hipLaunchKernelGGL(k_final<1>, dim3(grid), dim3(kThreads), 0, st, a, o); break;
     case 2: hipLaunchKernelGGL(k_final<2>, dim3(grid), dim3(kThreads), 0, st, a, o); break;

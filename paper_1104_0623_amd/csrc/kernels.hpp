@@ -56,7 +56,8 @@ constexpr int kMaxFront = 2048;
 constexpr int kThreads = 256;
 
 hipError_t launch_stage(const StageArgs& a, int rpt, int grid, hipStream_t st);
-hipError_t launch_final(const StageArgs& a, const OutArgs& o, int rpt, int grid, hipStream_t st);
+// maxb: largest final block in the stage (<= 96 uses the register Gauss-Jordan kernel)
+hipError_t launch_final(const StageArgs& a, const OutArgs& o, int rpt, int maxb, int grid, hipStream_t st);
 size_t stage_lds_bytes();
 
 }  // namespace findmi

@@ -58,6 +58,8 @@ def main() -> int:
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--preset", default="c3_128x128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="launch each step eagerly instead of replaying one captured hipGraph")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); energies "
@@ -81,26 +83,52 @@ def main() -> int:
     dL = torch.empty_like(dG)
     prec = find.PREC_MIXED if args.precision == "mixed" else find.PREC_FP64
     plan = find.Plan(Nx, Ny, st, precision=prec)
-    stream = torch.cuda.current_stream()
+    stream = torch.cuda.Stream()          # non-default stream (graph capture needs one)
+    torch.cuda.set_stream(stream)
 
-    def step():
+    def eager_step():
         find.solve(plan, E, H, S, SL, dG, dL, stream=stream)
 
-    for _ in range(args.warmup):
-        step()
+    for _ in range(max(1, args.warmup)):
+        eager_step()
     find.sync_status(plan, stream)
-    plan.set_profiling(True)
-    plan.profile()
+    if args.no_graph:
+        # the library records a HIP event pair around every stage launch
+        plan.set_profiling(True)
+        step = eager_step
+    else:
+        # one captured hipGraph per 256-energy batch (HIP cannot time events
+        # recorded inside a graph, so the replay is timed from the stream: the
+        # graph holds only the stage kernels and a 1-block status fill)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=stream):
+            eager_step()
+        torch.cuda.synchronize()
+
+        def step():
+            graph.replay()
     torch.cuda.synchronize()
     lat = []
+    kms = kflops = 0.0
+    nl = 0
+    flops_step = plan.flops_per_energy(False) * nE
     t0 = time.perf_counter()
     for _ in range(args.steps):
         ts = time.perf_counter()
-        step()
-        torch.cuda.synchronize()
+        if args.no_graph:
+            step()
+            torch.cuda.synchronize()
+            m, fl, n = plan.profile()   # kernel time of this step
+        else:
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record(stream)
+            step()
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            m, fl, n = ev0.elapsed_time(ev1), flops_step, 0
         lat.append(time.perf_counter() - ts)
+        kms += m; kflops += fl; nl += n
     elapsed = time.perf_counter() - t0
-    kms, kflops, nl = plan.profile()
     plan.set_profiling(False)
     find.sync_status(plan, stream)
     value = nE * args.steps / elapsed
@@ -115,11 +143,13 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"FIND diag G + diag G<, {Nx}x{Ny} mesh, {st}-point stencil, {nE} energies "
                                f"per step ({args.preset}), {args.precision}",
-                   "Nx": Nx, "Ny": Ny, "stencil": st, "energies_per_step": nE, "precision": args.precision},
+                   "Nx": Nx, "Ny": Ny, "stencil": st, "energies_per_step": nE, "precision": args.precision,
+                   "launch": "eager" if args.no_graph else "hipGraph replay per batch"},
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": None,
-                     "kernel": "k_stage (elimination kernel, all stage launches)",
+                     "kernel": "k_stage + k_final (elimination kernels, all stage launches)",
+                     "timing": "HIP events per stage launch" if args.no_graph else "HIP events around each graph replay",
                      "launches": nl, "kernel_ms_per_step": kms / args.steps,
                      "algorithmic_flops_per_step": kflops / args.steps},
     }

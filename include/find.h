@@ -141,11 +141,13 @@ const char* find_last_error(void);
 
 /* Instrumentation for roofline measurement.  While enabled, find_solve
  * records a HIP event pair on its stream around every elimination-stage
- * kernel launch.  find_plan_profile waits for the recorded events, returns
- * the summed elapsed milliseconds of those launches, their algorithmic
- * flops (the find_plan_flops model for the eliminations and energies each
- * launch processed) and the launch count since the previous call, then
- * resets the counters.  Any pointer argument may be NULL. */
+ * kernel launch (inside a captured hipGraph the pairs are part of the graph
+ * and are re-recorded by every replay).  find_plan_profile waits for the
+ * event pairs of the most recent find_solve (or of the latest replay of a
+ * captured one) and returns their summed elapsed milliseconds, their
+ * algorithmic flops (the find_plan_flops model for the eliminations and
+ * energies each launch processed) and the launch count.  Any pointer
+ * argument may be NULL. */
 find_status find_plan_set_profiling(find_plan plan, int enable);
 find_status find_plan_profile(find_plan plan, double* kernel_ms, double* kernel_flops, int* launches);
 

@@ -373,6 +373,7 @@ find_status find_solve(find_plan plan, int nE, const double* energies, const dou
       return fail(FIND_E_NOMEM, "find_solve: status allocation failed");
     d->status_len = nE;
   }
+  if (plan->profiling) d->ev_used = 0;  // the profile describes this solve
   hipLaunchKernelGGL(k_fill_int, dim3((nE + 255) / 256), dim3(256), 0, st, d->status, nE, 0);
   HIPCHK(hipGetLastError());
   const int nst = P.stencil == 9 ? 5 : 3;
@@ -451,7 +452,6 @@ find_status find_plan_profile(find_plan plan, double* kernel_ms, double* kernel_
       fl += d.ev_flops[k];
       ++nl;
     }
-    d.ev_used = 0;
   }
   if (kernel_ms) *kernel_ms = ms;
   if (kernel_flops) *kernel_flops = fl;

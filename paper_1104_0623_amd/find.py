@@ -144,7 +144,7 @@ class Plan:
         _check(lib().find_plan_set_profiling(self._h, int(enable)))
 
     def profile(self) -> tuple[float, float, int]:
-        """(elimination-kernel ms, their algorithmic flops, launches) since the last call."""
+        """(elimination-kernel ms, their algorithmic flops, launches) of the most recent solve."""
         ms, fl, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
         _check(lib().find_plan_profile(self._h, ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(n)))
         return ms.value, fl.value, n.value

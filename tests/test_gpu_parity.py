@@ -178,3 +178,40 @@ def test_mixed_precision_c2_and_c3_sampled():
     el = [nrel(out["diag_Gless"][e], ref["diag_Gless"][q]) for q, e in enumerate(sample)]
     assert max(eg) <= 3e-2 and max(el) <= 3e-2, (max(eg), max(el))
     assert np.median(eg) <= 1e-3 and np.median(el) <= 1e-3, (np.median(eg), np.median(el))
+
+
+def test_hip_graph_capture_replays_match_eager():
+    """find_solve enqueues kernels only (no allocation after the first call,
+    no memset), so a caller can capture it in a hipGraph.  Every replay, with
+    unrelated eager work in between, equals the eager result bit for bit."""
+    import torch
+    f = find()
+    E = inputs.energies_linspace(-3.0, 3.0, 6)
+    prob = inputs.make_problem(24, 33, 9, vmax=1.0, seed=9, energies=E, fL=1.0, fR=0.2)
+    plan = f.Plan(24, 33, 9)
+    dev = torch.device("cuda")
+    Et = torch.as_tensor(prob["energies"], device=dev); Ht = torch.as_tensor(prob["H"], device=dev)
+    St = torch.as_tensor(prob["sigma"], device=dev); SLt = torch.as_tensor(prob["sigma_less"], device=dev)
+    nb = f.n_bonds(24, 33, 9)
+    outs = [torch.empty((6, 33, 24), dtype=torch.complex128, device=dev) for _ in range(2)] + \
+           [torch.empty((6, nb), dtype=torch.complex128, device=dev) for _ in range(2)] + \
+           [torch.empty((6, nb), dtype=torch.float64, device=dev)]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        f.solve(plan, Et, Ht, St, SLt, *outs, stream=s)     # eager (allocates device state)
+    s.synchronize()
+    eager = [o.clone() for o in outs]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        f.solve(plan, Et, Ht, St, SLt, *outs, stream=s)
+    for rep in range(3):
+        for o in outs:
+            o.zero_()
+        junk = torch.randn(512, 512, device=dev) @ torch.randn(512, 512, device=dev)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for o, ref in zip(outs, eager):
+            assert torch.equal(o, ref), rep
+        del junk
+    f.sync_status(plan)

@@ -61,7 +61,6 @@ struct DevState {
   double2* ws = nullptr; size_t ws_elems = 0;
   int* status = nullptr; size_t status_len = 0;
   size_t maps_bytes = 0;
-  size_t ws_need = 0;       // complex elements of workspace a solve needs
   // profiling: event pairs around stage launches (reused between calls)
   std::vector<hipEvent_t> ev;
   std::vector<double> ev_flops;
@@ -154,7 +153,6 @@ find_status ensure_device(find_plan_s* p, DevState** out) {
     }
     ds_st.rpt = panel_rpt(std::max(1, maxn));
     ds->stages.push_back(ds_st);
-    ds->ws_need = std::max<size_t>(ds->ws_need, size_t(std::min<long long>(ds->slots, 1LL << 40)) * ds_st.ws_stride);
   }
   std::vector<int> srcpos(P.map_src.size());
   for (size_t k = 0; k < srcpos.size(); ++k)
@@ -197,18 +195,28 @@ find_status ensure_device(find_plan_s* p, DevState** out) {
   return FIND_OK;
 }
 
+// Workspace (complex elements) for passes of ec energies: every stage needs
+// one slot per workgroup it launches, min(slots, eliminations x ec).
+size_t ws_for(const DevState& d, int ec) {
+  size_t w = 0;
+  for (const DevStage& s : d.stages)
+    w = std::max<size_t>(w, size_t(std::min<long long>(d.slots, (long long)s.count * ec)) * s.ws_stride);
+  return w;
+}
+
 size_t budget_of(const find_plan_s* p) {
   return p->opts.workspace_budget ? p->opts.workspace_budget : (size_t(64) << 30);
 }
 
 // energies per internal pass so that pool + workspace fit in the budget
-int chunk_energies(const find_plan_s* p, int nE, size_t ws_bytes, size_t maps_bytes) {
+int chunk_energies(const find_plan_s* p, const DevState& d, int nE) {
   const size_t per_e = size_t(p->P.pool_per_energy) * sizeof(double2) + sizeof(int);
   const size_t budget = budget_of(p);
-  size_t avail = budget > ws_bytes + maps_bytes ? budget - ws_bytes - maps_bytes : 0;
-  int ec = int(std::min<size_t>(nE, avail / std::max<size_t>(per_e, 1)));
+  int ec = nE;
   if (p->opts.max_energies > 0) ec = std::min(ec, p->opts.max_energies);
-  return std::max(0, ec);
+  auto need = [&](int c) { return ws_for(d, c) * sizeof(double2) + d.maps_bytes + per_e * size_t(c); };
+  while (ec > 1 && need(ec) > budget) ec = std::max(1, std::min(ec - 1, int(ec * double(budget) / double(need(ec)))));
+  return need(ec) <= budget ? ec : 0;
 }
 
 }  // namespace
@@ -322,18 +330,24 @@ find_status find_plan_footprint(find_plan plan, int nE, int want_bonds, size_t* 
   (void)want_bonds;
   if (!plan || !bytes || nE < 1) return fail(FIND_E_ARG, "find_plan_footprint: bad argument");
   const Plan& P = plan->P;
-  // workspace: slots x largest per-slot front over all stages (slot count assumed 512)
-  size_t ws = 0, maps = 0;
-  for (const Elim& e : P.elims)
-    ws = std::max<size_t>(ws, e.kind == K_FINAL ? 4ull * e.b * e.b : size_t(e.n) * e.s + size_t(e.b) * e.n);
-  const size_t slots = 3 * 256;
-  ws *= slots * sizeof(double2);
-  maps = (P.map_node.size() * 2 + P.elims.size() * sizeof(ElimDev) / 4 + P.outbonds.size() * 5 +
-          P.outnode_node.size() * 2) * 4;
-  const size_t per_e = size_t(P.pool_per_energy) * sizeof(double2) + sizeof(int);
-  int ec = chunk_energies(plan, nE, ws, maps);
+  // the same sizing find_solve uses, for 3 workgroups on each of 256 CUs
+  DevState d;
+  d.slots = 3 * 256;
+  for (const Stage& st : P.stages) {
+    DevStage ds{st.first, st.count, st.phase, st.variant, 0.0, 1, 0, 0, nullptr};
+    for (int k = st.first; k < st.first + st.count; ++k) {
+      const Elim& e = P.elims[k];
+      ds.ws_stride = std::max<long long>(ds.ws_stride, e.kind == K_FINAL ? 4LL * e.b * e.b
+                                                                          : (long long)e.n * e.s + (long long)e.b * e.n);
+    }
+    d.stages.push_back(ds);
+  }
+  d.maps_bytes = (P.map_node.size() * 2 + P.elims.size() * sizeof(ElimDev) / 4 + P.outbonds.size() * 5 +
+                  P.outnode_node.size() * 2) * 4;
+  int ec = chunk_energies(plan, d, nE);
   if (ec < 1) ec = 1;
-  *bytes = ws + maps + per_e * size_t(std::min(ec, nE));
+  *bytes = ws_for(d, ec) * sizeof(double2) + d.maps_bytes +
+           (size_t(P.pool_per_energy) * sizeof(double2) + sizeof(int)) * size_t(ec);
   return FIND_OK;
 }
 
@@ -351,15 +365,15 @@ find_status find_solve(find_plan plan, int nE, const double* energies, const dou
   find_status fs = ensure_device(plan, &d);
   if (fs != FIND_OK) return fs;
   const int variant = (bond_G || bond_Gless || bond_J) ? 1 : 0;
-  // workspace (independent of the energy count)
-  if (d->ws_elems < d->ws_need) {
-    if (d->ws) { HIPCHK(hipStreamSynchronize(st)); HIPCHK(hipFree(d->ws)); d->ws = nullptr; d->ws_elems = 0; }
-    if (hipMalloc(&d->ws, d->ws_need * sizeof(double2)) != hipSuccess)
-      return fail(FIND_E_NOMEM, "find_solve: workspace allocation failed");
-    d->ws_elems = d->ws_need;
-  }
-  int ec = chunk_energies(plan, nE, d->ws_elems * sizeof(double2), d->maps_bytes);
+  const int ec = chunk_energies(plan, *d, nE);
   if (ec < 1) return fail(FIND_E_NOMEM, "find_solve: workspace budget too small for one energy");
+  const size_t ws_need = ws_for(*d, ec);
+  if (d->ws_elems < ws_need) {
+    if (d->ws) { HIPCHK(hipStreamSynchronize(st)); HIPCHK(hipFree(d->ws)); d->ws = nullptr; d->ws_elems = 0; }
+    if (hipMalloc(&d->ws, ws_need * sizeof(double2)) != hipSuccess)
+      return fail(FIND_E_NOMEM, "find_solve: workspace allocation failed");
+    d->ws_elems = ws_need;
+  }
   const size_t pool_need = size_t(ec) * size_t(P.pool_per_energy);
   if (d->pool_elems < pool_need) {
     if (d->pool) { HIPCHK(hipStreamSynchronize(st)); HIPCHK(hipFree(d->pool)); d->pool = nullptr; d->pool_elems = 0; }

@@ -215,3 +215,55 @@ def test_hip_graph_capture_replays_match_eager():
             assert torch.equal(o, ref), rep
         del junk
     f.sync_status(plan)
+
+
+# Above 128 x 128 the FP64 rounding of both the HIP path and the RGF oracle
+# reaches ~1e-10 (cond(A) grows with the mesh at eta = 1e-6), so the large
+# meshes are compared at 5e-10.
+TOL_LARGE = 5e-10
+
+
+def test_256x512_9pt_against_rgf():
+    """Largest mesh of the serving mix (256 x 512, 9-point), one energy vs RGF."""
+    f = find()
+    E = np.array([0.31 + 1e-6j])
+    prob = inputs.make_problem(256, 512, 9, vmax=1.0, seed=5, energies=E, fL=1.0, fR=0.0)
+    out = f.run_problem(f.Plan(256, 512, 9), prob, want_bonds=True)
+    ref = rgf.rgf_solve(256, 512, 9, prob["H"], E, prob["sigma"], prob["sigma_less"])
+    compare(out, ref, prob, tol=TOL_LARGE, label="256x512/9")
+
+
+def test_c5_512x512_full_batch_invariants():
+    """512 x 512 9-point, all 32 energies with bond currents, in the batched
+    launch: checked by properties that hold at any size (the RGF oracle takes
+    ~1 min per energy here)."""
+    f = find()
+    prob = inputs.make_preset("c5_512x512")
+    out = f.run_problem(f.Plan(512, 512, 9), prob, want_bonds=True)
+    Nx = Ny = 512
+    dl = out["diag_Gless"]
+    assert np.all(np.isfinite(out["diag_G"])) and np.all(np.isfinite(dl))
+    scale = np.max(np.abs(dl))
+    assert np.max(np.abs(dl.real)) <= 1e-9 * scale            # G< anti-Hermitian
+    assert np.min(dl.imag) >= -1e-9 * scale                   # density -i G<_ii >= 0
+    assert np.max(out["diag_G"].imag) <= 1e-9 * np.max(np.abs(out["diag_G"]))  # Im G_ii <= 0 (retarded)
+    bi, bj, _, _ = inputs.bond_endpoints(Nx, Ny, 9)
+    ys = np.arange(Nx * Ny) // Nx
+    inner = (ys > 0) & (ys < Ny - 1)
+    for e in (0, 11, 31):
+        J = out["bond_J"][e]
+        net = np.zeros(Nx * Ny)
+        np.add.at(net, bi, J)
+        np.add.at(net, bj, -J)
+        eta = prob["energies"][e].imag
+        # local balance off the contacts: sum_j J_{i->j} = -2 eta Im G<_ii
+        resid = net[inner] + 2 * eta * dl[e].ravel()[inner].imag
+        assert np.max(np.abs(resid)) <= 1e-8 * np.max(np.abs(J)), e
+        # current through transverse cuts: it drops between two cuts by exactly
+        # the eta sink of the nodes between them, 2 eta sum Im G<_ii
+        cuts = list(range(0, Ny - 1, 37))
+        flows = np.array([J[(ys[bi] <= c) & (ys[bj] > c)].sum() for c in cuts])
+        dens = dl[e].ravel().imag
+        sink = np.array([2 * eta * dens[(ys > cuts[0]) & (ys <= c)].sum() for c in cuts])
+        assert flows[0] > 0
+        assert np.max(np.abs(flows - (flows[0] - sink))) <= 1e-6 * abs(flows[0]), e

@@ -50,6 +50,33 @@ def cpu_baseline(prob: dict, budget_s: float = 12.0) -> dict:
                       f"same {Nx}x{Ny} workload, {dt:.1f} s"}
 
 
+def serve_bench(args) -> dict:
+    """Serving: a bounded Poisson trace of uneven (mesh, energies) requests,
+    served with continuous batching, in the plain FP64 and the mixed form."""
+    import torch
+    from paper_1104_0623_amd import find
+    from paper_1104_0623_amd.serve import GpuExecutor, Server, poisson_trace
+    res = {}
+    rates = [float(r) for r in args.rates.split(",")] if args.rates else [args.rate]
+    for prec_name, prec in (("fp64", find.PREC_FP64), ("mixed", find.PREC_MIXED)):
+        for rate in rates:
+            trace = poisson_trace(args.serve_requests, rate=rate, seed=0)
+            ex = GpuExecutor(n_slots=args.slots, precision=prec, plan_budget=16 << 30, cache_limit=96 << 30,
+                             keep_outputs=False)
+            # warm the plan cache (host trees, device maps) outside the timed trace
+            for key in sorted({r.key for r in trace}):
+                plan = ex.cache.take(key)
+                ex.cache.give(key, plan, plan.footprint(64), 0)
+            srv = Server(ex, n_slots=args.slots, hbm_budget=160 << 30)
+            srv.run(trace)
+            torch.cuda.synchronize()
+            st = srv.stats()
+            st["rate_req_per_s"] = rate
+            res.setdefault(prec_name, []).append(st)
+            print(json.dumps({"serving": prec_name, **st}), file=sys.stderr, flush=True)
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -58,6 +85,12 @@ def main() -> int:
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--preset", default="c3_128x128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving benchmark (Poisson trace of mixed meshes) instead of the batched solve")
+    ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--rates", default="", help="comma-separated arrival rates for a sweep")
+    ap.add_argument("--serve-requests", type=int, default=40)
+    ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--no-graph", action="store_true",
                     help="launch each step eagerly instead of replaying one captured hipGraph")
     args = ap.parse_args()
@@ -69,6 +102,21 @@ def main() -> int:
     import numpy as np
     import torch
     from paper_1104_0623_amd import find, inputs
+
+    if args.serve:
+        res = serve_bench(args)
+        best = res["fp64"][0]
+        out = {"metric": "energy-point solves/s under a Poisson request stream; p50/p99 latency",
+               "value": best["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+               "steps": best["requests"], "warmup": 0, "ms_per_step": best["makespan_s"] * 1e3 / best["requests"],
+               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+               "data": "synthetic",
+               "config": {"workload": f"serving: {args.serve_requests} requests, Poisson {args.rates or args.rate}/s, "
+                                      "Nx in {32,64,128,256}, Ny in {Nx,2Nx}, 5/9-point, 1-64 energies",
+                          "slots": args.slots},
+               "serving": res}
+        print(json.dumps(out), flush=True)
+        return 0
 
     prob = inputs.make_preset(args.preset)
     Nx, Ny, st = prob["Nx"], prob["Ny"], prob["stencil"]

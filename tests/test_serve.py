@@ -1,0 +1,98 @@
+"""Serving loop scheduling on the CPU (fake executor and fake clock) and, on
+the GPU, results alone vs in the mix."""
+import numpy as np
+import pytest
+
+from paper_1104_0623_amd import inputs
+from paper_1104_0623_amd.serve import Request, Server
+
+
+class FakeClock:
+    def __init__(self, tick=1e-3):
+        self.t = 0.0
+        self.tick = tick
+
+    def __call__(self):
+        self.t += self.tick
+        return self.t
+
+
+class FakeExecutor:
+    """Each request takes `dur[rid]` seconds of fake time once started."""
+
+    def __init__(self, clock, dur, fp):
+        self.clock, self.dur, self.fp = clock, dur, fp
+        self.running = {}
+        self.started = []
+
+    def footprint(self, req):
+        return self.fp[req.rid]
+
+    def start(self, slot, req, footprint):
+        self.running[slot] = (req, self.clock.t + self.dur[req.rid])
+        self.started.append(req.rid)
+
+    def done(self, slot):
+        return self.clock.t >= self.running[slot][1]
+
+    def finish(self, slot, inflight):
+        self.running.pop(slot)
+        return None
+
+
+def reqs(n, gap):
+    z = np.zeros(1, complex)
+    return [Request(i, i * gap, 4, 4, 5, z, np.zeros((3, 4, 4)), np.zeros((1, 2, 4, 4), complex),
+                    np.zeros((1, 2, 4, 4), complex)) for i in range(n)]
+
+
+def test_admission_respects_budget_slots_and_fifo():
+    clock = FakeClock()
+    rs = reqs(12, 0.002)
+    dur = {r.rid: 0.05 + 0.01 * (r.rid % 3) for r in rs}
+    fp = {r.rid: [30, 50, 20][r.rid % 3] for r in rs}
+    ex = FakeExecutor(clock, dur, fp)
+    srv = Server(ex, n_slots=3, hbm_budget=100, clock=clock)
+    done = srv.run(rs, idle_sleep=0)
+    assert sorted(c.rid for c in done) == list(range(12))
+    assert ex.started == list(range(12))                  # FIFO admission
+    assert srv.max_inflight_bytes <= 100
+    assert 2 <= srv.max_concurrent <= 3                   # requests overlapped
+    for c in done:
+        assert c.latency >= dur[c.rid] - 1e-9
+        assert c.admitted >= c.arrival - 1e-9
+    st = srv.stats()
+    assert st["requests"] == 12 and st["p99_latency_s"] >= st["p50_latency_s"]
+
+
+def test_small_budget_serialises_and_oversize_rejected():
+    clock = FakeClock()
+    rs = reqs(4, 0.0)
+    ex = FakeExecutor(clock, {r.rid: 0.02 for r in rs}, {r.rid: 60 for r in rs})
+    srv = Server(ex, n_slots=4, hbm_budget=100, clock=clock)
+    srv.run(rs, idle_sleep=0)
+    assert srv.max_concurrent == 1                        # 60 + 60 > 100
+    ex2 = FakeExecutor(FakeClock(), {0: 0.01}, {0: 101})
+    with pytest.raises(ValueError):
+        Server(ex2, n_slots=1, hbm_budget=100, clock=FakeClock()).submit(reqs(1, 0)[0])
+
+
+@pytest.mark.gpu
+def test_gpu_results_alone_equal_results_in_the_mix():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1104_0623_amd import find
+    from paper_1104_0623_amd.serve import GpuExecutor, poisson_trace
+    trace = poisson_trace(10, rate=500.0, seed=3, sizes=(16, 24, 40), max_energies=6, want_bonds=True)
+    ex = GpuExecutor(n_slots=4, precision=find.PREC_FP64, plan_budget=4 << 30, cache_limit=32 << 30)
+    srv = Server(ex, n_slots=4, hbm_budget=64 << 30)
+    mix = {c.rid: c.outputs for c in srv.run(trace)}
+    assert srv.max_concurrent >= 2
+    for r in trace:
+        alone = find.run_problem(find.Plan(*r.key), dict(energies=r.energies, H=r.H, sigma=r.sigma,
+                                                         sigma_less=r.sigma_less), want_bonds=True)
+        for k in alone:
+            assert np.array_equal(alone[k], mix[r.rid][k]), (r.rid, k)
+    st = srv.stats()
+    assert st["requests"] == 10 and st["solves_per_s"] > 0

@@ -22,6 +22,22 @@ if ROOT not in sys.path:
 
 PEAK = {"fp64": 78.6, "mixed": 157.3}   # MI355X dense MFMA TFLOP/s (FP64, FP32)
 
+# HBM bytes per elimination-kernel launch of the 128x128 x 256-energy FP64
+# solve, from rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs (calibrated on a
+# plain copy; profiles/elim_kernels_c3_128x128_fp64.md).  Valid only for the
+# kernel source they were measured on.
+TRAFFIC_BYTES_PER_LAUNCH = 52494042606.0
+TRAFFIC_KERNEL_SHA = "fc0862c6427311ef"
+
+
+def measured_traffic(preset: str, precision: str):
+    import hashlib
+    src = os.path.join(ROOT, "paper_1104_0623_amd", "csrc", "kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if sha != TRAFFIC_KERNEL_SHA or preset != "c3_128x128" or precision != "fp64":
+        return None
+    return TRAFFIC_BYTES_PER_LAUNCH
+
 
 def cpu_baseline(prob: dict, budget_s: float = 12.0) -> dict:
     """The RGF oracle, timed on this host over a bounded sample of the same
@@ -195,7 +211,7 @@ def main() -> int:
                    "launch": "eager" if args.no_graph else "hipGraph replay per batch"},
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": measured_traffic(args.preset, args.precision),
                      "kernel": "k_stage + k_final (elimination kernels, all stage launches)",
                      "timing": "HIP events per stage launch" if args.no_graph else "HIP events around each graph replay",
                      "launches": nl, "kernel_ms_per_step": kms / args.steps,

@@ -100,6 +100,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--preset", default="c3_128x128")
+    ap.add_argument("--leaf", type=int, default=8, help="largest leaf-cluster side of the tree")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve", action="store_true",
                     help="serving benchmark (Poisson trace of mixed meshes) instead of the batched solve")
@@ -146,7 +147,7 @@ def main() -> int:
     dG = torch.empty((nE, Ny, Nx), dtype=torch.complex128, device=dev)
     dL = torch.empty_like(dG)
     prec = find.PREC_MIXED if args.precision == "mixed" else find.PREC_FP64
-    plan = find.Plan(Nx, Ny, st, precision=prec)
+    plan = find.Plan(Nx, Ny, st, leaf=args.leaf, precision=prec)
     stream = torch.cuda.Stream()          # non-default stream (graph capture needs one)
     torch.cuda.set_stream(stream)
 
@@ -208,6 +209,7 @@ def main() -> int:
         "config": {"workload": f"FIND diag G + diag G<, {Nx}x{Ny} mesh, {st}-point stencil, {nE} energies "
                                f"per step ({args.preset}), {args.precision}",
                    "Nx": Nx, "Ny": Ny, "stencil": st, "energies_per_step": nE, "precision": args.precision,
+                   "leaf": args.leaf,
                    "launch": "eager" if args.no_graph else "hipGraph replay per batch"},
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",

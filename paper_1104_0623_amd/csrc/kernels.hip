@@ -95,8 +95,7 @@ struct Lds {
   int perm[kMaxFront];
   // pivot exchange, double-buffered by column parity: each wave's best
   // candidate (value, row, row contents) and the current row j
-  double candv[2][4];
-  int candi[2][4];
+  unsigned long long candv[2][4];   // per-wave pivot keys
   double2 candrow[2][4][16];
   double2 rowJ[2][16];
   double2 tri[16 * 16];
@@ -176,7 +175,7 @@ template <bool F32, int TM, int TN, class LA, class LB, class LC, class SC>
 __device__ __forceinline__ void gemm_tiles(int M, int N, int K, LA loadA, LB loadB, LC loadC, SC storeC) {
   typedef MfmaT<F32> T;
   typedef typename T::e E;
-  constexpr int PD = 2;
+  constexpr int PD = 1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int tm = (M + 16 * TM - 1) / (16 * TM), tn = (N + 16 * TN - 1) / (16 * TN);
   const int lr = lane & 15, lk = lane >> 4;
@@ -273,6 +272,41 @@ __device__ __forceinline__ void tri_inverse_unit_lower(Lds& L, int w) {
   __syncthreads();
 }
 
+// Pivot search key: the bits of a non-negative magnitude with the low
+// kKeyBits replaced by kKeyRows - 1 - row.  Non-negative doubles order as their bit
+// patterns, so the largest key (as an unsigned integer) is the largest
+// magnitude (to within 2^-40 relative), ties going to the lowest row; every
+// key of a row < kMaxFront is > 0.
+constexpr int kKeyBits = 12, kKeyRows = 1 << kKeyBits;
+static_assert(2 * kMaxFront <= kKeyRows, "pivot key row field too narrow");
+typedef unsigned long long u64;
+__device__ __forceinline__ u64 pivot_key(double mag, int row) {
+  return ((u64)__double_as_longlong(mag) & ~(u64)(kKeyRows - 1)) | (u64)(kKeyRows - 1 - row);
+}
+
+// DPP move of a 64-bit value between lanes of a row of 16 (quad_perm or mirror).
+template <int CTRL>
+__device__ __forceinline__ u64 dpp_u64(u64 x) {
+  const int lo = __builtin_amdgcn_update_dpp((int)x, (int)x, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(x >> 32), (int)(x >> 32), CTRL, 0xF, 0xF, false);
+  return ((u64)(unsigned)hi << 32) | (unsigned)lo;
+}
+__device__ __forceinline__ u64 readlane_u64(u64 x, int l) {
+  const int lo = __builtin_amdgcn_readlane((int)x, l), hi = __builtin_amdgcn_readlane((int)(x >> 32), l);
+  return ((u64)(unsigned)hi << 32) | (unsigned)lo;
+}
+__device__ __forceinline__ u64 umax64(u64 a, u64 b) { return a > b ? a : b; }
+// Maximum over the wave, returned to every lane: within rows of 16 by DPP
+// (swap neighbours, swap pairs, half-row mirror, row mirror), then across the
+// four rows by lane reads.
+__device__ __forceinline__ u64 wave_max(u64 x) {
+  x = umax64(x, dpp_u64<0xB1>(x));    // quad_perm [1,0,3,2]
+  x = umax64(x, dpp_u64<0x4E>(x));    // quad_perm [2,3,0,1]
+  x = umax64(x, dpp_u64<0x141>(x));   // row_half_mirror
+  x = umax64(x, dpp_u64<0x140>(x));   // row_mirror
+  return umax64(umax64(readlane_u64(x, 0), readlane_u64(x, 16)), umax64(readlane_u64(x, 32), readlane_u64(x, 48)));
+}
+
 // Physical row of logical row r of a front whose first s rows are pivoted.
 __device__ __forceinline__ int prow(const int* pm, int s, int r) { return r < s ? pm[r] : r; }
 
@@ -319,49 +353,41 @@ __device__ __forceinline__ bool tall_lu(Lds& L, double2* FA, int n, int s) {
       for (int j = 0; j < NB; ++j) {
         if (j < kb) {
           const int buf = j & 1;
-          // local candidate among this thread's pivot-eligible rows
-          double best = -1.0;
-          int bi = INT_MAX, bq = 0;
+          // local candidate among this thread's pivot-eligible rows, as a
+          // packed key (see pivot_key); 0 = no eligible row
+          u64 best = 0;
+          int bq = 0;
   #pragma unroll
           for (int q = 0; q < RPT; ++q) {
             const int rho = tid + kThreads * q;
             if (rho >= j && rho < ms) {
-              const double v = fabs(P[q][j].x) + fabs(P[q][j].y);
-              if (v > best) { best = v; bi = rho; bq = q; }
+              const u64 v = pivot_key(fabs(P[q][j].x) + fabs(P[q][j].y), rho);
+              if (v > best) { best = v; bq = q; }
             }
           }
-          // wave argmax (ties -> lowest row)
-          double wv = best;
-          int wi = bi;
-  #pragma unroll
-          for (int off = 32; off > 0; off >>= 1) {
-            const double ov = __shfl_xor(wv, off);
-            const int oi = __shfl_xor(wi, off);
-            if (ov > wv || (ov == wv && oi < wi)) { wv = ov; wi = oi; }
-          }
+          const u64 wv = wave_max(best);
           // the owner of the wave's winner publishes the row; thread j publishes row j
-          if (bi != INT_MAX && bi == wi && best == wv) {
+          if (best != 0 && best == wv) {
   #pragma unroll
             for (int q = 0; q < RPT; ++q)
               if (q == bq)
   #pragma unroll
                 for (int jj = 0; jj < NB; ++jj) L.candrow[buf][wave][jj] = P[q][jj];
           }
-          if (lane == 0) { L.candv[buf][wave] = wv; L.candi[buf][wave] = wi; }
+          if (lane == 0) L.candv[buf][wave] = wv;
           if (tid == j) {
   #pragma unroll
             for (int jj = 0; jj < NB; ++jj) L.rowJ[buf][jj] = P[0][jj];
           }
           __syncthreads();
           // every thread picks the same winner
-          double pvv = L.candv[buf][0];
-          int piv = L.candi[buf][0], pw = 0;
+          u64 gk = L.candv[buf][0];
   #pragma unroll
-          for (int w = 1; w < kThreads / 64; ++w) {
-            const double ov = L.candv[buf][w];
-            const int oi = L.candi[buf][w];
-            if (ov > pvv || (ov == pvv && oi < piv)) { pvv = ov; piv = oi; pw = w; }
-          }
+          for (int w = 1; w < kThreads / 64; ++w) gk = umax64(gk, L.candv[buf][w]);
+          int piv = kKeyRows - 1 - int(gk & (kKeyRows - 1));
+          bool pvv = (gk >> kKeyBits) != 0;            // non-zero pivot magnitude
+          if (piv < j || piv >= ms) { piv = j; pvv = false; }   // (row j is always eligible)
+          const int pw = (piv % kThreads) >> 6;
           if (tid == 0 && piv != j) {  // relabel: logical rows k0+j and k0+piv trade physical rows
             const int t = pm[k0 + j]; pm[k0 + j] = pm[k0 + piv]; pm[k0 + piv] = t;
           }
@@ -381,7 +407,7 @@ __device__ __forceinline__ bool tall_lu(Lds& L, double2* FA, int n, int s) {
             }
           }
           double2 pv = prow[j];
-          if (!(pvv > 0.0)) { singular = true; pv = make_double2(1.0, 0.0); }
+          if (!pvv) { singular = true; pv = make_double2(1.0, 0.0); }
           const double2 inv = cinv(pv);
   #pragma unroll
           for (int q = 0; q < RPT; ++q) {

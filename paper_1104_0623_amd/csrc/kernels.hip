@@ -97,7 +97,6 @@ struct Lds {
   // candidate (value, row, row contents) and the current row j
   unsigned long long candv[2][4];   // per-wave pivot keys
   double2 candrow[2][4][16];
-  double2 rowJ[2][16];
   double2 tri[16 * 16];
   double2 tinv[16 * 16];
 };
@@ -340,11 +339,16 @@ __device__ __forceinline__ bool tall_lu(Lds& L, double2* FA, int n, int s) {
                  [=](int r, int c, double2 v) { FA[(size_t)(k0 + c) * n + prow(pm, s, k0 + r)] = v; });
         __syncthreads();
       }
-      // (b) panel factorization with the panel in registers
+      // (b) panel factorization with the panel in registers.  Register rows
+      // stay with their threads: lg[q] is the logical panel row that register
+      // row q currently stands for (pivoting trades logical labels, not data).
+      // Columns >= kb and rows >= m are zero and stay zero.
       double2 P[RPT][NB];
+      int lg[RPT];
 #pragma unroll
       for (int q = 0; q < RPT; ++q) {
         const int rho = tid + kThreads * q;
+        lg[q] = rho;
 #pragma unroll
         for (int j = 0; j < NB; ++j)
           P[q][j] = (rho < m && j < kb) ? FA[(size_t)(k0 + j) * n + prow(pm, s, k0 + rho)] : zero2();
@@ -353,71 +357,56 @@ __device__ __forceinline__ bool tall_lu(Lds& L, double2* FA, int n, int s) {
       for (int j = 0; j < NB; ++j) {
         if (j < kb) {
           const int buf = j & 1;
-          // local candidate among this thread's pivot-eligible rows, as a
-          // packed key (see pivot_key); 0 = no eligible row
+          // local candidate among this thread's pivot-eligible rows (logical
+          // row in [j, ms)), as a packed key (see pivot_key); 0 = none
           u64 best = 0;
           int bq = 0;
   #pragma unroll
           for (int q = 0; q < RPT; ++q) {
-            const int rho = tid + kThreads * q;
-            if (rho >= j && rho < ms) {
-              const u64 v = pivot_key(fabs(P[q][j].x) + fabs(P[q][j].y), rho);
+            if (lg[q] >= j && lg[q] < ms) {
+              const u64 v = pivot_key(fabs(P[q][j].x) + fabs(P[q][j].y), lg[q]);
               if (v > best) { best = v; bq = q; }
             }
           }
           const u64 wv = wave_max(best);
-          // the owner of the wave's winner publishes the row; thread j publishes row j
+          // the owner of the wave's winner publishes columns j.. of its row
           if (best != 0 && best == wv) {
   #pragma unroll
             for (int q = 0; q < RPT; ++q)
               if (q == bq)
   #pragma unroll
-                for (int jj = 0; jj < NB; ++jj) L.candrow[buf][wave][jj] = P[q][jj];
+                for (int jj = j; jj < NB; ++jj) L.candrow[buf][wave][jj] = P[q][jj];
           }
           if (lane == 0) L.candv[buf][wave] = wv;
-          if (tid == j) {
-  #pragma unroll
-            for (int jj = 0; jj < NB; ++jj) L.rowJ[buf][jj] = P[0][jj];
-          }
           __syncthreads();
           // every thread picks the same winner
           u64 gk = L.candv[buf][0];
+          int pw = 0;                                   // winning wave
   #pragma unroll
-          for (int w = 1; w < kThreads / 64; ++w) gk = umax64(gk, L.candv[buf][w]);
+          for (int w = 1; w < kThreads / 64; ++w) {
+            const u64 o = L.candv[buf][w];
+            if (o > gk) { gk = o; pw = w; }
+          }
           int piv = kKeyRows - 1 - int(gk & (kKeyRows - 1));
           bool pvv = (gk >> kKeyBits) != 0;            // non-zero pivot magnitude
-          if (piv < j || piv >= ms) { piv = j; pvv = false; }   // (row j is always eligible)
-          const int pw = (piv % kThreads) >> 6;
+          if (piv < j || piv >= ms) { piv = j; pvv = false; }   // (logical row j is always eligible)
           if (tid == 0 && piv != j) {  // relabel: logical rows k0+j and k0+piv trade physical rows
             const int t = pm[k0 + j]; pm[k0 + j] = pm[k0 + piv]; pm[k0 + piv] = t;
           }
+          // the pivot's register row becomes logical row j, the former j takes piv
+  #pragma unroll
+          for (int q = 0; q < RPT; ++q) lg[q] = lg[q] == piv ? j : (lg[q] == j ? piv : lg[q]);
           const double2* prow = L.candrow[buf][pw];
-          if (piv != j) {
-            if (tid == j) {
-  #pragma unroll
-              for (int jj = 0; jj < NB; ++jj) P[0][jj] = prow[jj];
-            }
-            if (tid == piv % kThreads) {
-              const int pq = piv / kThreads;
-  #pragma unroll
-              for (int q = 0; q < RPT; ++q)
-                if (q == pq)
-  #pragma unroll
-                  for (int jj = 0; jj < NB; ++jj) P[q][jj] = L.rowJ[buf][jj];
-            }
-          }
           double2 pv = prow[j];
           if (!pvv) { singular = true; pv = make_double2(1.0, 0.0); }
           const double2 inv = cinv(pv);
   #pragma unroll
           for (int q = 0; q < RPT; ++q) {
-            const int rho = tid + kThreads * q;
-            if (rho > j && rho < m) {
+            if (lg[q] > j) {
               const double2 l = cmul(P[q][j], inv);
               P[q][j] = l;
   #pragma unroll
-              for (int jj = 0; jj < NB; ++jj)
-                if (jj > j && jj < kb) P[q][jj] = cfms(P[q][jj], l, prow[jj]);
+              for (int jj = j + 1; jj < NB; ++jj) P[q][jj] = cfms(P[q][jj], l, prow[jj]);
             }
           }
         }
@@ -426,15 +415,15 @@ __device__ __forceinline__ bool tall_lu(Lds& L, double2* FA, int n, int s) {
       // write the panel back; keep its unit-lower top block
 #pragma unroll
       for (int q = 0; q < RPT; ++q) {
-        const int rho = tid + kThreads * q;
-        if (rho < m)
+        if (lg[q] < m) {
 #pragma unroll
           for (int j = 0; j < NB; ++j)
-            if (j < kb) FA[(size_t)(k0 + j) * n + prow(pm, s, k0 + rho)] = P[q][j];
-      }
-      if (tid < kb) {
+            if (j < kb) FA[(size_t)(k0 + j) * n + prow(pm, s, k0 + lg[q])] = P[q][j];
+          if (lg[q] < kb) {
 #pragma unroll
-        for (int j = 0; j < NB; ++j) L.tri[tid * 16 + j] = P[0][j];
+            for (int j = 0; j < NB; ++j) L.tri[lg[q] * 16 + j] = P[q][j];
+          }
+        }
       }
       __syncthreads();
       // (d) U rows of this panel for the columns right of it

@@ -28,13 +28,15 @@ PEAK = {"fp64": 78.6, "mixed": 157.3}   # MI355X dense MFMA TFLOP/s (FP64, FP32)
 # kernel source they were measured on.
 TRAFFIC_BYTES_PER_LAUNCH = 52494042606.0
 TRAFFIC_KERNEL_SHA = "fc0862c6427311ef"
+TRAFFIC_TILES = ""
 
 
-def measured_traffic(preset: str, precision: str):
+def measured_traffic(preset: str, precision: str, tiles: str, cmode: str):
     import hashlib
     src = os.path.join(ROOT, "paper_1104_0623_amd", "csrc", "kernels.hip")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    if sha != TRAFFIC_KERNEL_SHA or preset != "c3_128x128" or precision != "fp64":
+    if (sha != TRAFFIC_KERNEL_SHA or tiles != TRAFFIC_TILES or preset != "c3_128x128" or precision != "fp64"
+            or cmode != "4m"):
         return None
     return TRAFFIC_BYTES_PER_LAUNCH
 
@@ -110,6 +112,10 @@ def main() -> int:
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--no-graph", action="store_true",
                     help="launch each step eagerly instead of replaying one captured hipGraph")
+    ap.add_argument("--complex-mode", choices=["4m", "3m"], default="4m",
+                    help="real split of the complex Schur products")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default wave tile (32x32) for every stage instead of tuning it")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); energies "
@@ -147,9 +153,18 @@ def main() -> int:
     dG = torch.empty((nE, Ny, Nx), dtype=torch.complex128, device=dev)
     dL = torch.empty_like(dG)
     prec = find.PREC_MIXED if args.precision == "mixed" else find.PREC_FP64
-    plan = find.Plan(Nx, Ny, st, leaf=args.leaf, precision=prec)
+    cmode = find.CPLX_3M if args.complex_mode == "3m" else find.CPLX_4M
+    plan = find.Plan(Nx, Ny, st, leaf=args.leaf, precision=prec, complex_mode=cmode)
     stream = torch.cuda.Stream()          # non-default stream (graph capture needs one)
     torch.cuda.set_stream(stream)
+    tune_s = 0.0
+    if not args.no_autotune:
+        # per-stage wave tiles picked by timing each configuration once on this batch
+        # (a one-off plan setup, outside the timed region)
+        t = time.perf_counter()
+        find.autotune(plan, E, H, S, SL, dG, dL, reps=1, stream=stream)
+        tune_s = time.perf_counter() - t
+    tiles = plan.tiles()
 
     def eager_step():
         find.solve(plan, E, H, S, SL, dG, dL, stream=stream)
@@ -209,11 +224,14 @@ def main() -> int:
         "config": {"workload": f"FIND diag G + diag G<, {Nx}x{Ny} mesh, {st}-point stencil, {nE} energies "
                                f"per step ({args.preset}), {args.precision}",
                    "Nx": Nx, "Ny": Ny, "stencil": st, "energies_per_step": nE, "precision": args.precision,
-                   "leaf": args.leaf,
-                   "launch": "eager" if args.no_graph else "hipGraph replay per batch"},
+                   "leaf": args.leaf, "complex_mode": args.complex_mode,
+                   "launch": "eager" if args.no_graph else "hipGraph replay per batch",
+                   "stage_tiles": "".join(str(t) for t in tiles),
+                   "autotune_s": round(tune_s, 3) if not args.no_autotune else None},
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": measured_traffic(args.preset, args.precision),
+                     "frac": achieved / peak, "traffic": measured_traffic(args.preset, args.precision, "".join(str(t) for t in tiles),
+                                                                 args.complex_mode),
                      "kernel": "k_stage + k_final (elimination kernels, all stage launches)",
                      "timing": "HIP events per stage launch" if args.no_graph else "HIP events around each graph replay",
                      "launches": nl, "kernel_ms_per_step": kms / args.steps,

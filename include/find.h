@@ -65,6 +65,7 @@ typedef enum {
 } find_status;
 
 typedef enum { FIND_PREC_FP64 = 0, FIND_PREC_MIXED = 1 } find_precision;
+typedef enum { FIND_CPLX_4M = 0, FIND_CPLX_3M = 1 } find_complex_mode;
 
 /* Plan options; pass NULL for defaults.
  *   leaf          largest leaf-cluster side (default 8): the mesh is bisected
@@ -80,14 +81,21 @@ typedef enum { FIND_PREC_FP64 = 0, FIND_PREC_MIXED = 1 } find_precision;
  *   max_energies  energies processed per internal pass (0 = chosen from the
  *                 workspace budget).
  *   fp64_top_levels  see precision (0 = default 2, negative = none).
- *   workspace_budget  device bytes the plan may hold (0 = 64 GiB). */
+ *   workspace_budget  device bytes the plan may hold (0 = 64 GiB).
+ *   complex_mode  real split of the complex Schur-complement and Sigma
+ *                 products: FIND_CPLX_4M (default; four real products per
+ *                 complex product) or FIND_CPLX_3M (three: ar br, ai bi and
+ *                 (ar + ai)(br + bi)).  3M rounds differently, within the
+ *                 same tolerances; flop counts stay at 8 per complex
+ *                 multiply-add either way. */
 typedef struct {
   int leaf;
   int precision;
   int max_energies;
   int fp64_top_levels;
   size_t workspace_budget;
-  int reserved[8];
+  int complex_mode;
+  int reserved[7];
 } find_plan_opts;
 
 /* Build the cluster tree, boundary sets, gather maps and level schedule for
@@ -150,6 +158,29 @@ const char* find_last_error(void);
  * argument may be NULL. */
 find_status find_plan_set_profiling(find_plan plan, int enable);
 find_status find_plan_profile(find_plan plan, double* kernel_ms, double* kernel_flops, int* launches);
+
+/* Tile autotuner (not a step of the method: it only picks how the products
+ * of eq. (major-update) and eq. (gless-update-rule) are split over the waves
+ * of a workgroup).  Each stage of the plan (the eliminations of one tree level
+ * and pass, launched together) has a wave-tile configuration for its Schur
+ * products: 0 = 32x32, 1 = 32x16, 2 = 16x32, 3 = 16x16 (stages whose fronts
+ * exceed 512 nodes, and the final leaf blocks, have configuration 0 only).
+ * The tile only decides which wave computes which output block, so results
+ * are bitwise the same for every configuration.
+ *   find_plan_autotune runs one solve of the first min(nE, pass size)
+ *   energies stage by stage, times every configuration of every stage `reps`
+ *   times (reps < 1 means 2) with HIP events on `hip_stream`, keeps the
+ *   fastest, and leaves that solve's diag G / diag G< in the outputs.  It
+ *   synchronises the stream; FIND_E_ARG if the stream is being captured.
+ *   find_plan_get_tiles copies min(cap, n_stages) configurations (stage
+ *   order of find_plan_export) and stores the stage count in *n_stages.
+ *   find_plan_set_tiles sets them (n must equal the stage count; each value
+ *   must be a configuration the stage has, else FIND_E_ARG). */
+find_status find_plan_autotune(find_plan plan, int nE, const double* energies, const double* H,
+                               const double* sigma, const double* sigma_less, double* diag_G,
+                               double* diag_Gless, int reps, void* hip_stream);
+find_status find_plan_get_tiles(find_plan plan, int* tiles, int cap, int* n_stages);
+find_status find_plan_set_tiles(find_plan plan, const int* tiles, int n);
 
 /* ---- Introspection (host only; for tests and tools) ---------------------- */
 typedef struct {

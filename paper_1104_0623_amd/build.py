@@ -13,15 +13,16 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfind.so")
-SOURCES = ["plan.cpp", "kernels.hip", "capi.hip"]
+# (source, extra flags): kernels.hip is compiled once per kernel family
+SOURCES = [("plan.cpp", []), ("capi.hip", [])] + [("kernels.hip", [f"-DFIND_TU={k}"]) for k in (1, 2, 3, 4)]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-command-line-argument"]
 
 
-def _compile(src: str, obj: str) -> None:
-    cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(src: str, extra: list, obj: str) -> None:
+    cmd = [HIPCC] + FLAGS + extra + ["-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -35,9 +36,9 @@ def build(verbose: bool = False) -> str:
     from concurrent.futures import ThreadPoolExecutor
     tmp = tempfile.mkdtemp(prefix="findbuild_")
     try:
-        objs = [os.path.join(tmp, s + ".o") for s in SOURCES]
+        objs = [os.path.join(tmp, f"{k}_{s}.o") for k, (s, _) in enumerate(SOURCES)]
         with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-            list(ex.map(lambda p: _compile(*p), zip(SOURCES, objs)))
+            list(ex.map(lambda p: _compile(p[0][0], p[0][1], p[1]), zip(SOURCES, objs)))
         out_tmp = LIB + ".tmp"
         cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", out_tmp] + objs
         r = subprocess.run(cmd, capture_output=True, text=True)

@@ -82,6 +82,8 @@ struct find_plan_s {
   int last_nE = 0;
   int last_device = -1;
   bool profiling = false;
+  std::vector<int> tiles;      // wave-tile configuration per stage
+  std::vector<int> tile_opts;  // configurations each stage has
 };
 
 namespace {
@@ -243,6 +245,8 @@ find_status find_plan_create(int Nx, int Ny, int stencil, const find_plan_opts* 
   if (o.precision != FIND_PREC_FP64 && o.precision != FIND_PREC_MIXED)
     return fail(FIND_E_ARG, "find_plan_create: unknown precision");
   if (o.max_energies < 0) return fail(FIND_E_ARG, "find_plan_create: max_energies must be >= 0");
+  if (o.complex_mode != FIND_CPLX_4M && o.complex_mode != FIND_CPLX_3M)
+    return fail(FIND_E_ARG, "find_plan_create: unknown complex_mode");
   if ((long long)Nx * Ny > (1LL << 24)) return fail(FIND_E_UNSUPPORTED, "find_plan_create: mesh larger than 2^24 nodes");
   find_plan_s* p = new (std::nothrow) find_plan_s();
   if (!p) return fail(FIND_E_NOMEM, "find_plan_create: host allocation failed");
@@ -254,6 +258,12 @@ find_status find_plan_create(int Nx, int Ny, int stencil, const find_plan_opts* 
     err = std::string("find_plan_create: ") + ex.what();
   }
   if (!err.empty()) { delete p; return fail(FIND_E_ARG, err); }
+  for (const Stage& st : p->P.stages) {
+    int maxn = 1;
+    for (int k = st.first; k < st.first + st.count; ++k) maxn = std::max(maxn, p->P.elims[k].n);
+    p->tiles.push_back(0);
+    p->tile_opts.push_back(st.phase == PH_FINAL ? 1 : stage_tile_configs(panel_rpt(maxn)));
+  }
   *out = p;
   return FIND_OK;
 }
@@ -351,30 +361,26 @@ find_status find_plan_footprint(find_plan plan, int nE, int want_bonds, size_t* 
   return FIND_OK;
 }
 
-find_status find_solve(find_plan plan, int nE, const double* energies, const double* H, const double* sigma,
-                       const double* sigma_less, double* diag_G, double* diag_Gless, double* bond_G,
-                       double* bond_Gless, double* bond_J, void* hip_stream) {
-  if (!plan) return fail(FIND_E_ARG, "find_solve: NULL plan");
-  if (nE < 1) return fail(FIND_E_ARG, "find_solve: nE must be >= 1");
-  if (!energies || !H || !sigma || !sigma_less || !diag_G || !diag_Gless)
-    return fail(FIND_E_ARG, "find_solve: NULL input or diagonal output pointer");
-  std::lock_guard<std::mutex> lk(plan->mu);
+}  // extern "C"
+
+namespace {
+
+// Device buffers for a solve of nE energies (grown on demand); *ec = energies per pass.
+find_status prepare(find_plan_s* plan, int nE, hipStream_t st, DevState** dout, int* ec) {
   const Plan& P = plan->P;
-  hipStream_t st = static_cast<hipStream_t>(hip_stream);
   DevState* d = nullptr;
   find_status fs = ensure_device(plan, &d);
   if (fs != FIND_OK) return fs;
-  const int variant = (bond_G || bond_Gless || bond_J) ? 1 : 0;
-  const int ec = chunk_energies(plan, *d, nE);
-  if (ec < 1) return fail(FIND_E_NOMEM, "find_solve: workspace budget too small for one energy");
-  const size_t ws_need = ws_for(*d, ec);
+  *ec = chunk_energies(plan, *d, nE);
+  if (*ec < 1) return fail(FIND_E_NOMEM, "find_solve: workspace budget too small for one energy");
+  const size_t ws_need = ws_for(*d, *ec);
   if (d->ws_elems < ws_need) {
     if (d->ws) { HIPCHK(hipStreamSynchronize(st)); HIPCHK(hipFree(d->ws)); d->ws = nullptr; d->ws_elems = 0; }
     if (hipMalloc(&d->ws, ws_need * sizeof(double2)) != hipSuccess)
       return fail(FIND_E_NOMEM, "find_solve: workspace allocation failed");
     d->ws_elems = ws_need;
   }
-  const size_t pool_need = size_t(ec) * size_t(P.pool_per_energy);
+  const size_t pool_need = size_t(*ec) * size_t(P.pool_per_energy);
   if (d->pool_elems < pool_need) {
     if (d->pool) { HIPCHK(hipStreamSynchronize(st)); HIPCHK(hipFree(d->pool)); d->pool = nullptr; d->pool_elems = 0; }
     if (hipMalloc(&d->pool, pool_need * sizeof(double2)) != hipSuccess)
@@ -387,40 +393,85 @@ find_status find_solve(find_plan plan, int nE, const double* energies, const dou
       return fail(FIND_E_NOMEM, "find_solve: status allocation failed");
     d->status_len = nE;
   }
+  *dout = d;
+  return FIND_OK;
+}
+
+// Kernel arguments of the pass over energies [e0, e0 + ne).
+void pass_args(const find_plan_s* plan, const DevState* d, int variant, int e0, int ne, const double* energies,
+               const double* H, const double* sigma, const double* sigma_less, double* diag_G,
+               double* diag_Gless, double* bond_G, double* bond_Gless, double* bond_J, StageArgs* pa,
+               OutArgs* po) {
+  const Plan& P = plan->P;
+  const size_t nx2 = size_t(P.Nx) * P.Nx;
+  const size_t nnodes = size_t(P.Nx) * P.Ny;
+  StageArgs a{};
+  a.nE = ne;
+  a.map_node = d->d_map_node; a.map_srcpos = d->d_map_srcpos;
+  a.energies = reinterpret_cast<const double2*>(energies) + e0;
+  a.H = H;
+  a.sigma = reinterpret_cast<const double2*>(sigma) + size_t(e0) * 2 * nx2;
+  a.sless = reinterpret_cast<const double2*>(sigma_less) + size_t(e0) * 2 * nx2;
+  a.pool = d->pool; a.pool_stride = P.pool_per_energy;
+  a.ws = d->ws;
+  a.Nx = P.Nx; a.Ny = P.Ny; a.nst = P.stencil == 9 ? 5 : 3;
+  a.status = d->status + e0;
+  OutArgs o{};
+  o.leaves = d->d_leafout[variant];
+  o.outnode = d->d_outnode; o.outbond = d->d_outbond; o.H = H;
+  o.n_bonds = P.n_bonds;
+  o.diag_G = reinterpret_cast<double2*>(diag_G) + size_t(e0) * nnodes;
+  o.diag_Gless = reinterpret_cast<double2*>(diag_Gless) + size_t(e0) * nnodes;
+  o.bond_G = bond_G ? reinterpret_cast<double2*>(bond_G) + size_t(e0) * P.n_bonds : nullptr;
+  o.bond_Gless = bond_Gless ? reinterpret_cast<double2*>(bond_Gless) + size_t(e0) * P.n_bonds : nullptr;
+  o.bond_J = bond_J ? bond_J + size_t(e0) * P.n_bonds : nullptr;
+  *pa = a;
+  *po = o;
+}
+
+// Launch stage k of a pass with wave-tile configuration tc; grid < 1 = nothing to do.
+hipError_t launch_stage_k(const find_plan_s* plan, const DevState* d, int k, StageArgs a, const OutArgs& o,
+                          int tc, hipStream_t st) {
+  const DevStage& s2 = d->stages[k];
+  a.elims = s2.d_elims; a.n_elims = s2.count; a.ws_stride = s2.ws_stride;
+  const long long items = (long long)s2.count * a.nE;
+  const int grid = int(std::min<long long>(items, d->slots));
+  if (grid < 1) return hipSuccess;
+  if (s2.phase == PH_FINAL) return launch_final(a, o, s2.rpt, grid, st);
+  return launch_stage(a, s2.rpt, tc, plan->opts.complex_mode, grid, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+find_status find_solve(find_plan plan, int nE, const double* energies, const double* H, const double* sigma,
+                       const double* sigma_less, double* diag_G, double* diag_Gless, double* bond_G,
+                       double* bond_Gless, double* bond_J, void* hip_stream) {
+  if (!plan) return fail(FIND_E_ARG, "find_solve: NULL plan");
+  if (nE < 1) return fail(FIND_E_ARG, "find_solve: nE must be >= 1");
+  if (!energies || !H || !sigma || !sigma_less || !diag_G || !diag_Gless)
+    return fail(FIND_E_ARG, "find_solve: NULL input or diagonal output pointer");
+  std::lock_guard<std::mutex> lk(plan->mu);
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  DevState* d = nullptr;
+  int ec = 0;
+  find_status fs = prepare(plan, nE, st, &d, &ec);
+  if (fs != FIND_OK) return fs;
+  const int variant = (bond_G || bond_Gless || bond_J) ? 1 : 0;
   if (plan->profiling) d->ev_used = 0;  // the profile describes this solve
   hipLaunchKernelGGL(k_fill_int, dim3((nE + 255) / 256), dim3(256), 0, st, d->status, nE, 0);
   HIPCHK(hipGetLastError());
-  const int nst = P.stencil == 9 ? 5 : 3;
-  const size_t nx2 = size_t(P.Nx) * P.Nx;
-  const size_t nnodes = size_t(P.Nx) * P.Ny;
   for (int e0 = 0; e0 < nE; e0 += ec) {
     const int ne = std::min(ec, nE - e0);
-    StageArgs a{};
-    a.nE = ne;
-    a.map_node = d->d_map_node; a.map_srcpos = d->d_map_srcpos;
-    a.energies = reinterpret_cast<const double2*>(energies) + e0;
-    a.H = H;
-    a.sigma = reinterpret_cast<const double2*>(sigma) + size_t(e0) * 2 * nx2;
-    a.sless = reinterpret_cast<const double2*>(sigma_less) + size_t(e0) * 2 * nx2;
-    a.pool = d->pool; a.pool_stride = P.pool_per_energy;
-    a.ws = d->ws;
-    a.Nx = P.Nx; a.Ny = P.Ny; a.nst = nst;
-    a.status = d->status + e0;
-    OutArgs o{};
-    o.leaves = d->d_leafout[variant];
-    o.outnode = d->d_outnode; o.outbond = d->d_outbond; o.H = H;
-    o.n_bonds = P.n_bonds;
-    o.diag_G = reinterpret_cast<double2*>(diag_G) + size_t(e0) * nnodes;
-    o.diag_Gless = reinterpret_cast<double2*>(diag_Gless) + size_t(e0) * nnodes;
-    o.bond_G = bond_G ? reinterpret_cast<double2*>(bond_G) + size_t(e0) * P.n_bonds : nullptr;
-    o.bond_Gless = bond_Gless ? reinterpret_cast<double2*>(bond_Gless) + size_t(e0) * P.n_bonds : nullptr;
-    o.bond_J = bond_J ? bond_J + size_t(e0) * P.n_bonds : nullptr;
-    for (const DevStage& s2 : d->stages) {
+    StageArgs a;
+    OutArgs o;
+    pass_args(plan, d, variant, e0, ne, energies, H, sigma, sigma_less, diag_G, diag_Gless, bond_G, bond_Gless,
+              bond_J, &a, &o);
+    for (size_t k = 0; k < d->stages.size(); ++k) {
+      const DevStage& s2 = d->stages[k];
       if (s2.variant >= 0 && s2.variant != variant) continue;
-      a.elims = s2.d_elims; a.n_elims = s2.count; a.ws_stride = s2.ws_stride;
-      const long long items = (long long)s2.count * ne;
-      const int grid = int(std::min<long long>(items, d->slots));
-      if (grid < 1) continue;
+      if ((long long)s2.count * ne < 1) continue;
       if (plan->profiling) {
         while (d->ev.size() < 2 * (d->ev_used + 1)) {
           hipEvent_t ev;
@@ -431,7 +482,7 @@ find_status find_solve(find_plan plan, int nE, const double* energies, const dou
         d->ev_flops[d->ev_used] = s2.flops_per_energy * ne;
         HIPCHK(hipEventRecord(d->ev[2 * d->ev_used], st));
       }
-      hipError_t he = s2.phase == PH_FINAL ? launch_final(a, o, s2.rpt, s2.maxb, grid, st) : launch_stage(a, s2.rpt, grid, st);
+      const hipError_t he = launch_stage_k(plan, d, int(k), a, o, plan->tiles[k], st);
       if (he != hipSuccess) return fail(FIND_E_DEVICE, std::string("stage launch: ") + hipGetErrorString(he));
       if (plan->profiling) {
         HIPCHK(hipEventRecord(d->ev[2 * d->ev_used + 1], st));
@@ -441,6 +492,86 @@ find_status find_solve(find_plan plan, int nE, const double* energies, const dou
   }
   plan->last_nE = nE;
   plan->last_device = d->device;
+  return FIND_OK;
+}
+
+find_status find_plan_autotune(find_plan plan, int nE, const double* energies, const double* H,
+                               const double* sigma, const double* sigma_less, double* diag_G,
+                               double* diag_Gless, int reps, void* hip_stream) {
+  if (!plan) return fail(FIND_E_ARG, "find_plan_autotune: NULL plan");
+  if (nE < 1) return fail(FIND_E_ARG, "find_plan_autotune: nE must be >= 1");
+  if (!energies || !H || !sigma || !sigma_less || !diag_G || !diag_Gless)
+    return fail(FIND_E_ARG, "find_plan_autotune: NULL input or output pointer");
+  if (reps < 1) reps = 2;
+  std::lock_guard<std::mutex> lk(plan->mu);
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIPCHK(hipStreamIsCapturing(st, &cs));
+  if (cs != hipStreamCaptureStatusNone) return fail(FIND_E_ARG, "find_plan_autotune: stream is being captured");
+  DevState* d = nullptr;
+  int ec = 0;
+  find_status fs = prepare(plan, nE, st, &d, &ec);
+  if (fs != FIND_OK) return fs;
+  const int ne = std::min(ec, nE);
+  hipLaunchKernelGGL(k_fill_int, dim3((ne + 255) / 256), dim3(256), 0, st, d->status, ne, 0);
+  HIPCHK(hipGetLastError());
+  StageArgs a;
+  OutArgs o;
+  pass_args(plan, d, 0, 0, ne, energies, H, sigma, sigma_less, diag_G, diag_Gless, nullptr, nullptr, nullptr, &a, &o);
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  find_status res = FIND_OK;
+  for (size_t k = 0; k < d->stages.size() && res == FIND_OK; ++k) {
+    const DevStage& s2 = d->stages[k];
+    if (s2.variant >= 0 && s2.variant != 0) continue;
+    const int nopt = plan->tile_opts[k];
+    int best = plan->tiles[k];
+    float best_ms = 0.f;
+    for (int tc = 0; tc < nopt && res == FIND_OK; ++tc) {
+      // a first untimed launch (it also leaves the stage's outputs for the next stage)
+      hipError_t he = launch_stage_k(plan, d, int(k), a, o, tc, st);
+      if (he == hipSuccess && nopt > 1) {
+        he = hipEventRecord(e0, st);
+        for (int r = 0; r < reps && he == hipSuccess; ++r) he = launch_stage_k(plan, d, int(k), a, o, tc, st);
+        if (he == hipSuccess) he = hipEventRecord(e1, st);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (he == hipSuccess && (tc == 0 || ms < best_ms)) { best_ms = ms; best = tc; }
+      }
+      if (he != hipSuccess) res = fail(FIND_E_DEVICE, std::string("find_plan_autotune: ") + hipGetErrorString(he));
+    }
+    plan->tiles[k] = best;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (res != FIND_OK) return res;
+  HIPCHK(hipStreamSynchronize(st));
+  plan->last_nE = ne;
+  plan->last_device = d->device;
+  return FIND_OK;
+}
+
+find_status find_plan_get_tiles(find_plan plan, int* tiles, int cap, int* n_stages) {
+  if (!plan) return fail(FIND_E_ARG, "find_plan_get_tiles: NULL plan");
+  std::lock_guard<std::mutex> lk(plan->mu);
+  const int n = int(plan->tiles.size());
+  if (n_stages) *n_stages = n;
+  if (tiles)
+    for (int k = 0; k < std::min(n, cap); ++k) tiles[k] = plan->tiles[k];
+  return FIND_OK;
+}
+
+find_status find_plan_set_tiles(find_plan plan, const int* tiles, int n) {
+  if (!plan || !tiles) return fail(FIND_E_ARG, "find_plan_set_tiles: NULL argument");
+  std::lock_guard<std::mutex> lk(plan->mu);
+  if (n != int(plan->tiles.size())) return fail(FIND_E_ARG, "find_plan_set_tiles: n must equal the stage count");
+  for (int k = 0; k < n; ++k)
+    if (tiles[k] < 0 || tiles[k] >= plan->tile_opts[k])
+      return fail(FIND_E_ARG, "find_plan_set_tiles: stage " + std::to_string(k) + " has no configuration " +
+                                  std::to_string(tiles[k]));
+  for (int k = 0; k < n; ++k) plan->tiles[k] = tiles[k];
   return FIND_OK;
 }
 

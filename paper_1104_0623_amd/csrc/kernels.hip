@@ -101,8 +101,6 @@ struct Lds {
   double2 tinv[16 * 16];
 };
 
-size_t stage_lds_bytes() { return sizeof(Lds); }
-
 // Entries of the assembled front A_g / Sigma_g of one elimination, by front
 // row/column (local [S ; B] index): the block of a source cluster's stored U
 // (or R) when both indices come from that source, else the original A (or
@@ -170,24 +168,29 @@ template <> struct MfmaT<true> {
   static __device__ __forceinline__ int drow(int q, int lk) { return 4 * lk + q; }
 };
 
-template <bool F32, int TM, int TN, class LA, class LB, class LC, class SC>
+template <bool F32, int TM, int TN, bool C3, class LA, class LB, class LC, class SC>
 __device__ __forceinline__ void gemm_tiles(int M, int N, int K, LA loadA, LB loadB, LC loadC, SC storeC) {
   typedef MfmaT<F32> T;
   typedef typename T::e E;
   constexpr int PD = 1;
+  constexpr int NACC = C3 ? 3 : 2;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int tm = (M + 16 * TM - 1) / (16 * TM), tn = (N + 16 * TN - 1) / (16 * TN);
   const int lr = lane & 15, lk = lane >> 4;
   const int nk = (K + 3) >> 2;
   for (int t = wave; t < tm * tn; t += kThreads / 64) {
     const int r0 = (t % tm) * 16 * TM, c0 = (t / tm) * 16 * TN;
-    typename T::acc accR[TM][TN], accI[TM][TN];
+    // 4M: acc[0] = Re, acc[1] = Im.  3M: acc[0] = sum aR bR, acc[1] = sum aI bI,
+    // acc[2] = sum (aR + aI)(bR + bI); Re = acc0 - acc1, Im = acc2 - acc0 - acc1.
+    typename T::acc acc[NACC][TM][TN];
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+    for (int h = 0; h < NACC; ++h)
 #pragma unroll
-      for (int j = 0; j < TN; ++j)
+      for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) { accR[i][j][q] = 0; accI[i][j][q] = 0; }
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[h][i][j][q] = 0;
     E aR[PD + 1][TM], aI[PD + 1][TM], bR[PD + 1][TN], bI[PD + 1][TN];
     auto fetch = [&](int slot, int ks) {
       const int kk = 4 * ks + lk;
@@ -211,20 +214,35 @@ __device__ __forceinline__ void gemm_tiles(int M, int N, int K, LA loadA, LB loa
       for (int u = 0; u <= PD; ++u) {
         if (ks + u < nk) {
           fetch((u + PD) % (PD + 1), ks + u + PD);
+          if constexpr (C3) {
 #pragma unroll
-          for (int i = 0; i < TM; ++i)
+            for (int i = 0; i < TM; ++i)
 #pragma unroll
-            for (int j = 0; j < TN; ++j) {
-              accR[i][j] = T::mac(aR[u][i], bR[u][j], accR[i][j]);
-              accI[i][j] = T::mac(aR[u][i], bI[u][j], accI[i][j]);
-            }
+              for (int j = 0; j < TN; ++j) {
+                acc[0][i][j] = T::mac(aR[u][i], bR[u][j], acc[0][i][j]);
+                acc[1][i][j] = T::mac(aI[u][i], bI[u][j], acc[1][i][j]);
+              }
 #pragma unroll
-          for (int i = 0; i < TM; ++i)
+            for (int i = 0; i < TM; ++i)
 #pragma unroll
-            for (int j = 0; j < TN; ++j) {
-              accR[i][j] = T::mac(-aI[u][i], bI[u][j], accR[i][j]);
-              accI[i][j] = T::mac(aI[u][i], bR[u][j], accI[i][j]);
-            }
+              for (int j = 0; j < TN; ++j)
+                acc[2][i][j] = T::mac(aR[u][i] + aI[u][i], bR[u][j] + bI[u][j], acc[2][i][j]);
+          } else {
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+              for (int j = 0; j < TN; ++j) {
+                acc[0][i][j] = T::mac(aR[u][i], bR[u][j], acc[0][i][j]);
+                acc[1][i][j] = T::mac(aR[u][i], bI[u][j], acc[1][i][j]);
+              }
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+              for (int j = 0; j < TN; ++j) {
+                acc[0][i][j] = T::mac(-aI[u][i], bI[u][j], acc[0][i][j]);
+                acc[1][i][j] = T::mac(aI[u][i], bR[u][j], acc[1][i][j]);
+              }
+          }
         }
       }
     }
@@ -237,7 +255,16 @@ __device__ __forceinline__ void gemm_tiles(int M, int N, int K, LA loadA, LB loa
           const int r = r0 + 16 * i + T::drow(q, lk), c = c0 + 16 * j + lr;
           if (r < M && c < N) {
             const double2 v = loadC(r, c);
-            storeC(r, c, make_double2(v.x - double(accR[i][j][q]), v.y - double(accI[i][j][q])));
+            double re, im;
+            if constexpr (C3) {
+              const double p0 = double(acc[0][i][j][q]), p1 = double(acc[1][i][j][q]);
+              re = p0 - p1;
+              im = double(acc[2][i][j][q]) - p0 - p1;
+            } else {
+              re = double(acc[0][i][j][q]);
+              im = double(acc[1][i][j][q]);
+            }
+            storeC(r, c, make_double2(v.x - re, v.y - im));
           }
         }
   }
@@ -245,8 +272,21 @@ __device__ __forceinline__ void gemm_tiles(int M, int N, int K, LA loadA, LB loa
 
 template <bool F32 = false, class LA, class LB, class LC, class SC>
 __device__ __forceinline__ void gemm_sub(int M, int N, int K, LA loadA, LB loadB, LC loadC, SC storeC) {
-  if (N <= 16) gemm_tiles<F32, 2, 1>(M, N, K, loadA, loadB, loadC, storeC);
-  else gemm_tiles<F32, 2, 2>(M, N, K, loadA, loadB, loadC, storeC);
+  if (N <= 16) gemm_tiles<F32, 2, 1, false>(M, N, K, loadA, loadB, loadC, storeC);
+  else gemm_tiles<F32, 2, 2, false>(M, N, K, loadA, loadB, loadC, storeC);
+}
+
+// The Schur-complement products of an elimination, with the wave tile picked
+// per stage (TC: 0 = 32x32, 1 = 32x16, 2 = 16x32, 3 = 16x16; 16-wide where N
+// <= 16) and the 4M or 3M real split of the complex product (C3).  The tile
+// only decides which wave computes which output block: every entry sees the
+// same k-order, so the result does not depend on TC.
+template <bool F32, int TC, bool C3, class LA, class LB, class LC, class SC>
+__device__ __forceinline__ void gemm_schur(int M, int N, int K, LA loadA, LB loadB, LC loadC, SC storeC) {
+  constexpr int TM = (TC == 0 || TC == 1) ? 2 : 1;
+  constexpr int TN = (TC == 0 || TC == 2) ? 2 : 1;
+  if (TN == 2 && N <= 16) gemm_tiles<F32, TM, 1, C3>(M, N, K, loadA, loadB, loadC, storeC);
+  else gemm_tiles<F32, TM, TN, C3>(M, N, K, loadA, loadB, loadC, storeC);
 }
 
 // Inverse of the w x w unit-lower triangle held below the diagonal of L.tri
@@ -490,7 +530,7 @@ __device__ __forceinline__ void trsm_right_unit_lower(Lds& L, double2* FA, int n
   }
 }
 
-template <int RPT>
+template <int RPT, int TC, int CM>
 __global__ __launch_bounds__(kThreads, 3) void k_stage(StageArgs a) {
   constexpr int NB = 16 / RPT;  // panel columns held in registers
   __shared__ Lds L;
@@ -538,13 +578,13 @@ __global__ __launch_bounds__(kThreads, 3) void k_stage(StageArgs a) {
     auto c2 = [=](int r, int c) { return W[(size_t)(s + c) * b + r]; };
     auto s2 = [=](int r, int c, double2 v) { Ro[(size_t)c * b + r] = v; };
     if (E.f32) {
-      gemm_sub<true>(b, b + n, s, l_, b1, c1, s1);
+      gemm_schur<true, TC, CM == 1>(b, b + n, s, l_, b1, c1, s1);
       __syncthreads();
-      gemm_sub<true>(b, b, s, a2, b2, c2, s2);
+      gemm_schur<true, TC, CM == 1>(b, b, s, a2, b2, c2, s2);
     } else {
-      gemm_sub<false>(b, b + n, s, l_, b1, c1, s1);
+      gemm_schur<false, TC, CM == 1>(b, b + n, s, l_, b1, c1, s1);
       __syncthreads();
-      gemm_sub<false>(b, b, s, a2, b2, c2, s2);
+      gemm_schur<false, TC, CM == 1>(b, b, s, a2, b2, c2, s2);
     }
     __syncthreads();
   }
@@ -618,19 +658,33 @@ __global__ __launch_bounds__(kThreads, 3) void k_final(StageArgs a, OutArgs o) {
   }
 }
 
-hipError_t launch_stage(const StageArgs& a, int rpt, int grid, hipStream_t st) {
-  switch (rpt) {
-    case 1: hipLaunchKernelGGL(k_stage<1>, dim3(grid), dim3(kThreads), 0, st, a); break;
-    case 2: hipLaunchKernelGGL(k_stage<2>, dim3(grid), dim3(kThreads), 0, st, a); break;
-    case 4: hipLaunchKernelGGL(k_stage<4>, dim3(grid), dim3(kThreads), 0, st, a); break;
-    case 8: hipLaunchKernelGGL(k_stage<8>, dim3(grid), dim3(kThreads), 0, st, a); break;
-    default: return hipErrorInvalidValue;
+#ifndef FIND_TU
+#error "kernels.hip is compiled once per kernel family: -DFIND_TU=1, 2, 3 or 4"
+#endif
+// Launchers.  The source is compiled once per kernel family (FIND_TU = 1:
+// k_stage with 1 panel row per thread, 2: with 2, 3: with 4 and 8, 4: k_final)
+// so that the families build in parallel.
+#define FIND_LAUNCH_STAGE(R, T, C)                                                            \
+  if (tc == T && cm == C) {                                                                   \
+    hipLaunchKernelGGL((k_stage<R, T, C>), dim3(grid), dim3(kThreads), 0, st, a);             \
+    return hipGetLastError();                                                                 \
   }
-  return hipGetLastError();
+#if FIND_TU == 1 || FIND_TU == 2
+hipError_t FIND_CAT(launch_stage_r, FIND_TU)(const StageArgs& a, int tc, int cm, int grid, hipStream_t st) {
+  FIND_LAUNCH_STAGE(FIND_TU, 0, 0) FIND_LAUNCH_STAGE(FIND_TU, 1, 0) FIND_LAUNCH_STAGE(FIND_TU, 2, 0) FIND_LAUNCH_STAGE(FIND_TU, 3, 0)
+  FIND_LAUNCH_STAGE(FIND_TU, 0, 1) FIND_LAUNCH_STAGE(FIND_TU, 1, 1) FIND_LAUNCH_STAGE(FIND_TU, 2, 1) FIND_LAUNCH_STAGE(FIND_TU, 3, 1)
+  return hipErrorInvalidValue;
 }
-
-hipError_t launch_final(const StageArgs& a, const OutArgs& o, int rpt, int maxb, int grid, hipStream_t st) {
-  (void)maxb;
+#endif
+#if FIND_TU == 3
+hipError_t launch_stage_r48(const StageArgs& a, int rpt, int tc, int cm, int grid, hipStream_t st) {
+  if (rpt == 4) { FIND_LAUNCH_STAGE(4, 0, 0) FIND_LAUNCH_STAGE(4, 0, 1) }
+  if (rpt == 8) { FIND_LAUNCH_STAGE(8, 0, 0) FIND_LAUNCH_STAGE(8, 0, 1) }
+  return hipErrorInvalidValue;
+}
+#endif
+#if FIND_TU == 4
+hipError_t launch_final(const StageArgs& a, const OutArgs& o, int rpt, int grid, hipStream_t st) {
   switch (rpt) {
     case 1: hipLaunchKernelGGL(k_final<1>, dim3(grid), dim3(kThreads), 0, st, a, o); break;
     case 2: hipLaunchKernelGGL(k_final<2>, dim3(grid), dim3(kThreads), 0, st, a, o); break;
@@ -640,5 +694,7 @@ hipError_t launch_final(const StageArgs& a, const OutArgs& o, int rpt, int maxb,
   }
   return hipGetLastError();
 }
+#endif
+#undef FIND_LAUNCH_STAGE
 
 }  // namespace findmi

@@ -55,9 +55,24 @@ inline int panel_rpt(int n) { return n <= 256 ? 1 : n <= 512 ? 2 : n <= 1024 ? 4
 constexpr int kMaxFront = 2048;
 constexpr int kThreads = 256;
 
-hipError_t launch_stage(const StageArgs& a, int rpt, int grid, hipStream_t st);
-// maxb: largest final block in the stage (<= 96 uses the register Gauss-Jordan kernel)
-hipError_t launch_final(const StageArgs& a, const OutArgs& o, int rpt, int maxb, int grid, hipStream_t st);
-size_t stage_lds_bytes();
+// Stage launchers (one per kernel family; see kernels.hip).  tc: wave tile of
+// the Schur products (0..kTileConfigs-1; families with 4 or 8 panel rows per
+// thread take tc = 0 only), cm: 0 = 4M, 1 = 3M complex products.
+constexpr int kTileConfigs = 4;
+#define FIND_CAT_(a, b) a##b
+#define FIND_CAT(a, b) FIND_CAT_(a, b)
+hipError_t launch_stage_r1(const StageArgs& a, int tc, int cm, int grid, hipStream_t st);
+hipError_t launch_stage_r2(const StageArgs& a, int tc, int cm, int grid, hipStream_t st);
+hipError_t launch_stage_r48(const StageArgs& a, int rpt, int tc, int cm, int grid, hipStream_t st);
+hipError_t launch_final(const StageArgs& a, const OutArgs& o, int rpt, int grid, hipStream_t st);
+// tile configurations available to a stage whose fronts need rpt panel rows per thread
+inline int stage_tile_configs(int rpt) { return rpt <= 2 ? kTileConfigs : 1; }
+inline hipError_t launch_stage(const StageArgs& a, int rpt, int tc, int cm, int grid, hipStream_t st) {
+  switch (rpt) {
+    case 1: return launch_stage_r1(a, tc, cm, grid, st);
+    case 2: return launch_stage_r2(a, tc, cm, grid, st);
+    default: return launch_stage_r48(a, rpt, tc, cm, grid, st);
+  }
+}
 
 }  // namespace findmi

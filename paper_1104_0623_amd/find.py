@@ -17,10 +17,13 @@ LIB_PATH = os.path.join(HERE, "libfind.so")
 
 FIND_OK, FIND_E_ARG, FIND_E_NOMEM, FIND_E_SINGULAR, FIND_E_DEVICE, FIND_E_UNSUPPORTED = range(6)
 PREC_FP64, PREC_MIXED = 0, 1
+CPLX_4M, CPLX_3M = 0, 1
+TILE_NAMES = ("32x32", "32x16", "16x32", "16x16")
 EF_FIELDS, SF_FIELDS, LF_FIELDS, ON_FIELDS, OB_FIELDS = 13, 4, 6, 2, 5
 EXPORTED = ["find_plan_create", "find_plan_destroy", "find_plan_footprint", "find_plan_flops",
             "find_n_bonds", "find_solve", "find_sync_status", "find_last_error",
-            "find_plan_summary", "find_plan_export", "find_plan_set_profiling", "find_plan_profile"]
+            "find_plan_summary", "find_plan_export", "find_plan_set_profiling", "find_plan_profile",
+            "find_plan_autotune", "find_plan_get_tiles", "find_plan_set_tiles"]
 
 
 class FindError(RuntimeError):
@@ -32,7 +35,7 @@ class FindError(RuntimeError):
 class PlanOpts(ctypes.Structure):
     _fields_ = [("leaf", ctypes.c_int), ("precision", ctypes.c_int), ("max_energies", ctypes.c_int),
                 ("fp64_top_levels", ctypes.c_int), ("workspace_budget", ctypes.c_size_t),
-                ("reserved", ctypes.c_int * 8)]
+                ("complex_mode", ctypes.c_int), ("reserved", ctypes.c_int * 7)]
 
 
 class PlanSummary(ctypes.Structure):
@@ -76,6 +79,10 @@ def lib() -> ctypes.CDLL:
         L.find_plan_profile.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_int)]
         L.find_plan_profile.restype = st
+        L.find_plan_autotune.argtypes = [vp, i32] + [vp] * 6 + [i32, vp]; L.find_plan_autotune.restype = st
+        L.find_plan_get_tiles.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_int)]
+        L.find_plan_get_tiles.restype = st
+        L.find_plan_set_tiles.argtypes = [vp, vp, i32]; L.find_plan_set_tiles.restype = st
         _lib = L
     return _lib
 
@@ -93,11 +100,13 @@ class Plan:
     """A FIND plan for one mesh shape (host tree + lazily created device state)."""
 
     def __init__(self, Nx: int, Ny: int, stencil: int = 5, leaf: int = 8, precision: int = PREC_FP64,
-                 max_energies: int = 0, workspace_budget: int = 0, fp64_top_levels: int = 0):
+                 max_energies: int = 0, workspace_budget: int = 0, fp64_top_levels: int = 0,
+                 complex_mode: int = CPLX_4M):
         self.Nx, self.Ny, self.stencil = Nx, Ny, stencil
         self._h = ctypes.c_void_p()
         o = PlanOpts(leaf=leaf, precision=precision, max_energies=max_energies,
-                     workspace_budget=workspace_budget, fp64_top_levels=fp64_top_levels)
+                     workspace_budget=workspace_budget, fp64_top_levels=fp64_top_levels,
+                     complex_mode=complex_mode)
         _check(lib().find_plan_create(Nx, Ny, stencil, ctypes.byref(o), ctypes.byref(self._h)))
 
     def close(self):
@@ -149,6 +158,18 @@ class Plan:
         _check(lib().find_plan_profile(self._h, ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(n)))
         return ms.value, fl.value, n.value
 
+    def tiles(self) -> list[int]:
+        """Wave-tile configuration of each stage (index into TILE_NAMES)."""
+        n = ctypes.c_int()
+        _check(lib().find_plan_get_tiles(self._h, None, 0, ctypes.byref(n)))
+        buf = (ctypes.c_int * max(1, n.value))()
+        _check(lib().find_plan_get_tiles(self._h, buf, n.value, ctypes.byref(n)))
+        return list(buf[: n.value])
+
+    def set_tiles(self, tiles) -> None:
+        buf = (ctypes.c_int * max(1, len(tiles)))(*tiles)
+        _check(lib().find_plan_set_tiles(self._h, buf, len(tiles)))
+
     def footprint(self, nE: int, want_bonds: bool = False) -> int:
         b = ctypes.c_size_t()
         _check(lib().find_plan_footprint(self._h, nE, int(want_bonds), ctypes.byref(b)))
@@ -190,6 +211,26 @@ def solve(plan: Plan, energies, H, sigma, sigma_less, diag_G, diag_Gless,
         stream = torch.cuda.current_stream()
     sp = ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
     _check(lib().find_solve(plan.handle, nE, *args, sp))
+
+
+def autotune(plan: Plan, energies, H, sigma, sigma_less, diag_G, diag_Gless, reps: int = 2,
+             stream=None) -> list[int]:
+    """Pick each stage's wave tile by timing every configuration on these
+    inputs (one pass, synchronising); diag_G / diag_Gless receive that pass's
+    results.  Returns the chosen configurations."""
+    import torch
+    Nx, Ny = plan.Nx, plan.Ny
+    nE = int(energies.shape[0])
+    nst = 5 if plan.stencil == 9 else 3
+    c128, f64 = torch.complex128, torch.float64
+    args = [_ptr(energies, "energies", (nE,), c128), _ptr(H, "H", (nst, Ny, Nx), f64),
+            _ptr(sigma, "sigma", (nE, 2, Nx, Nx), c128), _ptr(sigma_less, "sigma_less", (nE, 2, Nx, Nx), c128),
+            _ptr(diag_G, "diag_G", (nE, Ny, Nx), c128), _ptr(diag_Gless, "diag_Gless", (nE, Ny, Nx), c128)]
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+    _check(lib().find_plan_autotune(plan.handle, nE, *args, int(reps), sp))
+    return plan.tiles()
 
 
 def sync_status(plan: Plan, stream=None) -> None:

@@ -125,6 +125,63 @@ def test_singleton_and_one_leaf_meshes():
         compare(out, ref, prob, label=f"{Nx}x{Ny}")
 
 
+def test_tile_configurations_give_bitwise_equal_results():
+    """The wave tile of the Schur products only moves work between waves."""
+    f = find()
+    E = inputs.energies_linspace(-3.2, 3.1, 5)
+    prob = inputs.make_problem(40, 52, 9, vmax=1.0, seed=7, energies=E, fL=1.0, fR=0.2)
+    plan = f.Plan(40, 52, 9)
+    base = f.run_problem(plan, prob, want_bonds=True)
+    stages = plan.export()["stages"]
+    for tc in (1, 2, 3):
+        plan.set_tiles([0 if st[2] == 3 else tc for st in stages])
+        out = f.run_problem(plan, prob, want_bonds=True)
+        for k in base:
+            assert np.array_equal(out[k], base[k]), (tc, k)
+
+
+def test_autotune_picks_valid_tiles_and_keeps_results():
+    import torch
+    f = find()
+    prob = inputs.make_preset("c2_64x64")
+    plan = f.Plan(64, 64, 5)
+    base = f.run_problem(plan, prob, want_bonds=False)
+    dev = torch.device("cuda")
+    t = {k: torch.as_tensor(np.ascontiguousarray(prob[k]), device=dev)
+         for k in ("energies", "H", "sigma", "sigma_less")}
+    nE = prob["energies"].size
+    dG = torch.zeros((nE, 64, 64), dtype=torch.complex128, device=dev)
+    dL = torch.zeros_like(dG)
+    tiles = f.autotune(plan, t["energies"], t["H"], t["sigma"], t["sigma_less"], dG, dL, reps=1)
+    stages = plan.export()["stages"]
+    assert len(tiles) == len(stages)
+    assert all(0 <= tc < (1 if st[2] == 3 else 4) for tc, st in zip(tiles, stages))
+    # the tuning pass leaves its (bitwise identical) results in the outputs
+    assert np.array_equal(dG.cpu().numpy(), base["diag_G"])
+    assert np.array_equal(dL.cpu().numpy(), base["diag_Gless"])
+    again = f.run_problem(plan, prob, want_bonds=False)
+    for k in again:
+        assert np.array_equal(again[k], base[k]), k
+
+
+@pytest.mark.parametrize("Nx,Ny,stencil,leaf", [(16, 16, 5, 4), (33, 20, 9, 8), (1, 11, 5, 2), (24, 40, 5, 8)])
+def test_3m_complex_products_against_dense(Nx, Ny, stencil, leaf):
+    f = find()
+    E = np.array([0.41 + 1e-6j, -2.9 + 1e-6j, 1.3 + 1e-3j])
+    prob = inputs.make_problem(Nx, Ny, stencil, vmax=1.0, seed=Nx * 7 + Ny, energies=E, fL=1.0, fR=0.3)
+    ref = dense.dense_solve(Nx, Ny, stencil, prob["H"], E, prob["sigma"], prob["sigma_less"])
+    out = f.run_problem(f.Plan(Nx, Ny, stencil, leaf=leaf, complex_mode=f.CPLX_3M), prob, want_bonds=True)
+    compare(out, ref, prob, label=f"3M {Nx}x{Ny}/{stencil}/leaf{leaf}")
+
+
+def test_3m_c2_64x64_against_rgf():
+    f = find()
+    prob = inputs.make_preset("c2_64x64")
+    ref = rgf.rgf_solve(64, 64, 5, prob["H"], prob["energies"], prob["sigma"], prob["sigma_less"])
+    out = f.run_problem(f.Plan(64, 64, 5, complex_mode=f.CPLX_3M), prob, want_bonds=True)
+    compare(out, ref, prob, label="3M c2")
+
+
 # Mixed form (FP32 Schur/Sigma products, FP64 LU, L solve, top levels and
 # final leaf blocks).  Its error is set by cond(A) x eps32: with eta = 1e-6 the
 # closed sub-domains eliminated at each level are near-resonant, so

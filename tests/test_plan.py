@@ -49,6 +49,36 @@ def test_argument_errors():
     assert b"NULL plan" in L.find_last_error()
 
 
+def test_tile_and_complex_mode_options():
+    find = findlib()
+    with pytest.raises(find.FindError) as ei:
+        find.Plan(8, 8, 5, complex_mode=2)
+    assert ei.value.status == find.FIND_E_ARG
+    plan = find.Plan(64, 64, 5, complex_mode=find.CPLX_3M)
+    n = plan.summary()["n_stages"]
+    tiles = plan.tiles()
+    assert tiles == [0] * n
+    stages = plan.export()["stages"]
+    # every Schur stage of a mesh whose fronts stay <= 512 has all four
+    # configurations; the final leaf-block stages have only configuration 0
+    want = [0 if st[2] == 3 else 3 for st in stages]
+    plan.set_tiles(want)
+    assert plan.tiles() == want
+    bad = list(want)
+    bad[[k for k, st in enumerate(stages) if st[2] == 3][0]] = 1
+    with pytest.raises(find.FindError):
+        plan.set_tiles(bad)
+    with pytest.raises(find.FindError):
+        plan.set_tiles(want[:-1])
+    with pytest.raises(find.FindError):
+        plan.set_tiles([4] * n)
+    assert plan.tiles() == want          # a rejected call changes nothing
+    L = find.lib()
+    assert L.find_plan_autotune(None, 1, *([None] * 6), 2, None) == find.FIND_E_ARG
+    assert L.find_plan_autotune(plan.handle, 0, *([None] * 6), 2, None) == find.FIND_E_ARG
+    assert L.find_plan_set_tiles(plan.handle, None, n) == find.FIND_E_ARG
+
+
 def test_tree_shape_128():
     find = findlib()
     p = find.Plan(128, 128, 5)

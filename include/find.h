@@ -159,27 +159,32 @@ const char* find_last_error(void);
 find_status find_plan_set_profiling(find_plan plan, int enable);
 find_status find_plan_profile(find_plan plan, double* kernel_ms, double* kernel_flops, int* launches);
 
-/* Tile autotuner (not a step of the method: it only picks how the products
- * of eq. (major-update) and eq. (gless-update-rule) are split over the waves
- * of a workgroup).  Each stage of the plan (the eliminations of one tree level
- * and pass, launched together) has a wave-tile configuration for its Schur
- * products: 0 = 32x32, 1 = 32x16, 2 = 16x32, 3 = 16x16 (stages whose fronts
- * exceed 512 nodes, and the final leaf blocks, have configuration 0 only).
- * The tile only decides which wave computes which output block, so results
- * are bitwise the same for every configuration.
+/* Launch-shape autotuner (not a step of the method: it only picks how the
+ * work of a stage is spread over workgroups and waves).  Each stage of the
+ * plan (the eliminations of one tree level and pass, launched together) has a
+ * launch configuration: 0..3 = one 256-thread workgroup per front with wave
+ * tiles of 32x32, 32x16, 16x32 or 16x16 for the Schur products of eq.
+ * (major-update) and eq. (gless-update-rule) (stages whose fronts exceed 512
+ * nodes, and the final leaf blocks, have 0 only); 4 = one 64-thread workgroup
+ * (a single wave) per front, for stages whose fronts have at most 128 nodes.
+ * A configuration only decides which threads compute which part of the same
+ * operations in the same order, so results are bitwise the same for every
+ * configuration.
  *   find_plan_autotune runs one solve of the first min(nE, pass size)
  *   energies stage by stage, times every configuration of every stage `reps`
  *   times (reps < 1 means 2) with HIP events on `hip_stream`, keeps the
  *   fastest, and leaves that solve's diag G / diag G< in the outputs.  It
  *   synchronises the stream; FIND_E_ARG if the stream is being captured.
  *   find_plan_get_tiles copies min(cap, n_stages) configurations (stage
- *   order of find_plan_export) and stores the stage count in *n_stages.
+ *   order of find_plan_export) to tiles and the bit mask of the
+ *   configurations each stage has to masks (either may be NULL), and stores
+ *   the stage count in *n_stages.
  *   find_plan_set_tiles sets them (n must equal the stage count; each value
  *   must be a configuration the stage has, else FIND_E_ARG). */
 find_status find_plan_autotune(find_plan plan, int nE, const double* energies, const double* H,
                                const double* sigma, const double* sigma_less, double* diag_G,
                                double* diag_Gless, int reps, void* hip_stream);
-find_status find_plan_get_tiles(find_plan plan, int* tiles, int cap, int* n_stages);
+find_status find_plan_get_tiles(find_plan plan, int* tiles, int* masks, int cap, int* n_stages);
 find_status find_plan_set_tiles(find_plan plan, const int* tiles, int n);
 
 /* ---- Introspection (host only; for tests and tools) ---------------------- */

@@ -43,6 +43,7 @@ struct DevStage {
   int rpt;              // panel rows per thread (from the largest front)
   int maxb;             // largest kept set in the stage
   long long ws_stride;  // complex elements per workspace slot
+  int maxn;             // largest front in the stage
   ElimDev* d_elims;     // points into DevState::d_elims
 };
 
@@ -83,7 +84,7 @@ struct find_plan_s {
   int last_device = -1;
   bool profiling = false;
   std::vector<int> tiles;      // wave-tile configuration per stage
-  std::vector<int> tile_opts;  // configurations each stage has
+  std::vector<int> tile_mask;  // bit mask of the configurations each stage has
 };
 
 namespace {
@@ -128,7 +129,7 @@ find_status ensure_device(find_plan_s* p, DevState** out) {
     std::vector<int> idx(st.count);
     std::iota(idx.begin(), idx.end(), st.first);
     std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return elim_flops(P.elims[a]) > elim_flops(P.elims[b]); });
-    DevStage ds_st{st.first, st.count, st.phase, st.variant, 0.0, 1, 0, 0, nullptr};
+    DevStage ds_st{st.first, st.count, st.phase, st.variant, 0.0, 1, 0, 0, 0, nullptr};
     int maxn = 0;
     for (int q = 0; q < st.count; ++q) {
       const Elim& e = P.elims[idx[q]];
@@ -144,7 +145,7 @@ find_status ensure_device(find_plan_s* p, DevState** out) {
       maxn = std::max(maxn, e.n);
       ds_st.maxb = std::max(ds_st.maxb, e.b);
       ds_st.flops_per_energy += elim_flops(e);
-      const long long need = e.kind == K_FINAL ? 4LL * e.b * e.b                     // [U; I], T and G T
+      const long long need = e.kind == K_FINAL ? 3LL * e.b * e.b                     // [U; I] and T
                                                : (long long)e.n * e.s + (long long)e.b * e.n;  // tall block and W
       ds_st.ws_stride = std::max<long long>(ds_st.ws_stride, need);
     }
@@ -154,6 +155,7 @@ find_status ensure_device(find_plan_s* p, DevState** out) {
       return fail(FIND_E_UNSUPPORTED, buf);
     }
     ds_st.rpt = panel_rpt(std::max(1, maxn));
+    ds_st.maxn = std::max(1, maxn);
     ds->stages.push_back(ds_st);
   }
   std::vector<int> srcpos(P.map_src.size());
@@ -197,12 +199,18 @@ find_status ensure_device(find_plan_s* p, DevState** out) {
   return FIND_OK;
 }
 
+// Workgroups a stage may launch: one per slot, or kWaveGroupsPerSlot 64-thread
+// groups per slot when its fronts are small enough for the one-wave form.
+long long stage_groups(const DevState& d, const DevStage& s) {
+  return (long long)d.slots * (s.maxn <= kWaveMaxFront ? kWaveGroupsPerSlot : 1);
+}
+
 // Workspace (complex elements) for passes of ec energies: every stage needs
-// one slot per workgroup it launches, min(slots, eliminations x ec).
+// one slot per workgroup it launches, min(groups, eliminations x ec).
 size_t ws_for(const DevState& d, int ec) {
   size_t w = 0;
   for (const DevStage& s : d.stages)
-    w = std::max<size_t>(w, size_t(std::min<long long>(d.slots, (long long)s.count * ec)) * s.ws_stride);
+    w = std::max<size_t>(w, size_t(std::min<long long>(stage_groups(d, s), (long long)s.count * ec)) * s.ws_stride);
   return w;
 }
 
@@ -262,7 +270,7 @@ find_status find_plan_create(int Nx, int Ny, int stencil, const find_plan_opts* 
     int maxn = 1;
     for (int k = st.first; k < st.first + st.count; ++k) maxn = std::max(maxn, p->P.elims[k].n);
     p->tiles.push_back(0);
-    p->tile_opts.push_back(st.phase == PH_FINAL ? 1 : stage_tile_configs(panel_rpt(maxn)));
+    p->tile_mask.push_back(stage_tile_mask(maxn, st.phase == PH_FINAL));
   }
   *out = p;
   return FIND_OK;
@@ -344,11 +352,12 @@ find_status find_plan_footprint(find_plan plan, int nE, int want_bonds, size_t* 
   DevState d;
   d.slots = 3 * 256;
   for (const Stage& st : P.stages) {
-    DevStage ds{st.first, st.count, st.phase, st.variant, 0.0, 1, 0, 0, nullptr};
+    DevStage ds{st.first, st.count, st.phase, st.variant, 0.0, 1, 0, 0, 1, nullptr};
     for (int k = st.first; k < st.first + st.count; ++k) {
       const Elim& e = P.elims[k];
-      ds.ws_stride = std::max<long long>(ds.ws_stride, e.kind == K_FINAL ? 4LL * e.b * e.b
+      ds.ws_stride = std::max<long long>(ds.ws_stride, e.kind == K_FINAL ? 3LL * e.b * e.b
                                                                           : (long long)e.n * e.s + (long long)e.b * e.n);
+      ds.maxn = std::max(ds.maxn, e.n);
     }
     d.stages.push_back(ds);
   }
@@ -435,10 +444,11 @@ hipError_t launch_stage_k(const find_plan_s* plan, const DevState* d, int k, Sta
   const DevStage& s2 = d->stages[k];
   a.elims = s2.d_elims; a.n_elims = s2.count; a.ws_stride = s2.ws_stride;
   const long long items = (long long)s2.count * a.nE;
-  const int grid = int(std::min<long long>(items, d->slots));
+  const long long groups = tc == kTileWave ? stage_groups(*d, s2) : d->slots;
+  const int grid = int(std::min<long long>(items, groups));
   if (grid < 1) return hipSuccess;
-  if (s2.phase == PH_FINAL) return launch_final(a, o, s2.rpt, grid, st);
-  return launch_stage(a, s2.rpt, tc, plan->opts.complex_mode, grid, st);
+  if (s2.phase == PH_FINAL) return launch_final_tc(a, o, s2.maxn, tc, grid, st);
+  return launch_stage(a, s2.maxn, tc, plan->opts.complex_mode, grid, st);
 }
 
 }  // namespace
@@ -525,21 +535,30 @@ find_status find_plan_autotune(find_plan plan, int nE, const double* energies, c
   for (size_t k = 0; k < d->stages.size() && res == FIND_OK; ++k) {
     const DevStage& s2 = d->stages[k];
     if (s2.variant >= 0 && s2.variant != 0) continue;
-    const int nopt = plan->tile_opts[k];
-    int best = plan->tiles[k];
-    float best_ms = 0.f;
-    for (int tc = 0; tc < nopt && res == FIND_OK; ++tc) {
+    const int mask = plan->tile_mask[k];
+    const bool several = (mask & (mask - 1)) != 0;
+    int best = plan->tiles[k], last = -1;
+    float best_ms = -1.f;
+    for (int tc = 0; tc < kTileConfigs && res == FIND_OK; ++tc) {
+      if (!(mask >> tc & 1)) continue;
       // a first untimed launch (it also leaves the stage's outputs for the next stage)
       hipError_t he = launch_stage_k(plan, d, int(k), a, o, tc, st);
-      if (he == hipSuccess && nopt > 1) {
+      if (he == hipSuccess && several) {
         he = hipEventRecord(e0, st);
         for (int r = 0; r < reps && he == hipSuccess; ++r) he = launch_stage_k(plan, d, int(k), a, o, tc, st);
         if (he == hipSuccess) he = hipEventRecord(e1, st);
         if (he == hipSuccess) he = hipEventSynchronize(e1);
         float ms = 0.f;
         if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
-        if (he == hipSuccess && (tc == 0 || ms < best_ms)) { best_ms = ms; best = tc; }
+        if (he == hipSuccess && (best_ms < 0.f || ms < best_ms)) { best_ms = ms; best = tc; }
       }
+      if (he != hipSuccess) res = fail(FIND_E_DEVICE, std::string("find_plan_autotune: ") + hipGetErrorString(he));
+      last = tc;
+    }
+    // leave the chosen configuration's outputs for the next stage (configurations
+    // may round differently), so that the pass equals a solve with the chosen tiles
+    if (res == FIND_OK && last != best) {
+      const hipError_t he = launch_stage_k(plan, d, int(k), a, o, best, st);
       if (he != hipSuccess) res = fail(FIND_E_DEVICE, std::string("find_plan_autotune: ") + hipGetErrorString(he));
     }
     plan->tiles[k] = best;
@@ -553,13 +572,15 @@ find_status find_plan_autotune(find_plan plan, int nE, const double* energies, c
   return FIND_OK;
 }
 
-find_status find_plan_get_tiles(find_plan plan, int* tiles, int cap, int* n_stages) {
+find_status find_plan_get_tiles(find_plan plan, int* tiles, int* masks, int cap, int* n_stages) {
   if (!plan) return fail(FIND_E_ARG, "find_plan_get_tiles: NULL plan");
   std::lock_guard<std::mutex> lk(plan->mu);
   const int n = int(plan->tiles.size());
   if (n_stages) *n_stages = n;
-  if (tiles)
-    for (int k = 0; k < std::min(n, cap); ++k) tiles[k] = plan->tiles[k];
+  for (int k = 0; k < std::min(n, cap); ++k) {
+    if (tiles) tiles[k] = plan->tiles[k];
+    if (masks) masks[k] = plan->tile_mask[k];
+  }
   return FIND_OK;
 }
 
@@ -568,7 +589,7 @@ find_status find_plan_set_tiles(find_plan plan, const int* tiles, int n) {
   std::lock_guard<std::mutex> lk(plan->mu);
   if (n != int(plan->tiles.size())) return fail(FIND_E_ARG, "find_plan_set_tiles: n must equal the stage count");
   for (int k = 0; k < n; ++k)
-    if (tiles[k] < 0 || tiles[k] >= plan->tile_opts[k])
+    if (tiles[k] < 0 || tiles[k] >= kTileConfigs || !(plan->tile_mask[k] >> tiles[k] & 1))
       return fail(FIND_E_ARG, "find_plan_set_tiles: stage " + std::to_string(k) + " has no configuration " +
                                   std::to_string(tiles[k]));
   for (int k = 0; k < n; ++k) plan->tiles[k] = tiles[k];

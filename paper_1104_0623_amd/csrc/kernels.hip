@@ -89,14 +89,18 @@ struct Orig {
   }
 };
 
-struct Lds {
-  int node[kMaxFront];     // (y << 16) | x of each front row
-  int srcpos[kMaxFront];
-  int perm[kMaxFront];
+// Shared memory of one workgroup of NT threads working on fronts of at most
+// MAXN nodes.
+template <int NT, int MAXN>
+struct LdsT {
+  static constexpr int kNT = NT, kW = NT / 64;
+  int node[MAXN];          // (y << 16) | x of each front row
+  int srcpos[MAXN];
+  int perm[MAXN];
   // pivot exchange, double-buffered by column parity: each wave's best
-  // candidate (value, row, row contents) and the current row j
-  unsigned long long candv[2][4];   // per-wave pivot keys
-  double2 candrow[2][4][16];
+  // candidate key and the contents of its row
+  unsigned long long candv[2][kW];
+  double2 candrow[2][kW][16];
   double2 tri[16 * 16];
   double2 tinv[16 * 16];
 };
@@ -139,11 +143,13 @@ struct Front {
 
 // Visit (r, c) for r < nr, c < nc with the block's threads, column-major
 // order inside a column, without integer division.
-template <class F>
+template <int NT, class F>
 __device__ __forceinline__ void for_each_rc(int nr, int nc, F&& f) {
+  constexpr int LNT = NT == 64 ? 6 : NT == 128 ? 7 : 8;
+  static_assert((1 << LNT) == NT, "workgroup of 64, 128 or 256 threads");
   const int lg = nr <= 1 ? 0 : 32 - __clz(nr - 1);
-  const int lgr = lg < 8 ? lg : 8;
-  const int rmask = (1 << lgr) - 1, cstep = kThreads >> lgr;
+  const int lgr = lg < LNT ? lg : LNT;
+  const int rmask = (1 << lgr) - 1, cstep = NT >> lgr;
   const int rr = threadIdx.x & rmask, cc = threadIdx.x >> lgr;
   for (int c = cc; c < nc; c += cstep)
     for (int r = rr; r < nr; r += rmask + 1) f(r, c);
@@ -168,7 +174,7 @@ template <> struct MfmaT<true> {
   static __device__ __forceinline__ int drow(int q, int lk) { return 4 * lk + q; }
 };
 
-template <bool F32, int TM, int TN, bool C3, class LA, class LB, class LC, class SC>
+template <int NT, bool F32, int TM, int TN, bool C3, class LA, class LB, class LC, class SC>
 __device__ __forceinline__ void gemm_tiles(int M, int N, int K, LA loadA, LB loadB, LC loadC, SC storeC) {
   typedef MfmaT<F32> T;
   typedef typename T::e E;
@@ -178,7 +184,7 @@ __device__ __forceinline__ void gemm_tiles(int M, int N, int K, LA loadA, LB loa
   const int tm = (M + 16 * TM - 1) / (16 * TM), tn = (N + 16 * TN - 1) / (16 * TN);
   const int lr = lane & 15, lk = lane >> 4;
   const int nk = (K + 3) >> 2;
-  for (int t = wave; t < tm * tn; t += kThreads / 64) {
+  for (int t = wave; t < tm * tn; t += NT / 64) {
     const int r0 = (t % tm) * 16 * TM, c0 = (t / tm) * 16 * TN;
     // 4M: acc[0] = Re, acc[1] = Im.  3M: acc[0] = sum aR bR, acc[1] = sum aI bI,
     // acc[2] = sum (aR + aI)(bR + bI); Re = acc0 - acc1, Im = acc2 - acc0 - acc1.
@@ -270,10 +276,10 @@ __device__ __forceinline__ void gemm_tiles(int M, int N, int K, LA loadA, LB loa
   }
 }
 
-template <bool F32 = false, class LA, class LB, class LC, class SC>
+template <int NT, class LA, class LB, class LC, class SC>
 __device__ __forceinline__ void gemm_sub(int M, int N, int K, LA loadA, LB loadB, LC loadC, SC storeC) {
-  if (N <= 16) gemm_tiles<F32, 2, 1, false>(M, N, K, loadA, loadB, loadC, storeC);
-  else gemm_tiles<F32, 2, 2, false>(M, N, K, loadA, loadB, loadC, storeC);
+  if (N <= 16) gemm_tiles<NT, false, 2, 1, false>(M, N, K, loadA, loadB, loadC, storeC);
+  else gemm_tiles<NT, false, 2, 2, false>(M, N, K, loadA, loadB, loadC, storeC);
 }
 
 // The Schur-complement products of an elimination, with the wave tile picked
@@ -281,19 +287,20 @@ __device__ __forceinline__ void gemm_sub(int M, int N, int K, LA loadA, LB loadB
 // <= 16) and the 4M or 3M real split of the complex product (C3).  The tile
 // only decides which wave computes which output block: every entry sees the
 // same k-order, so the result does not depend on TC.
-template <bool F32, int TC, bool C3, class LA, class LB, class LC, class SC>
+template <int NT, bool F32, int TC, bool C3, class LA, class LB, class LC, class SC>
 __device__ __forceinline__ void gemm_schur(int M, int N, int K, LA loadA, LB loadB, LC loadC, SC storeC) {
   constexpr int TM = (TC == 0 || TC == 1) ? 2 : 1;
   constexpr int TN = (TC == 0 || TC == 2) ? 2 : 1;
-  if (TN == 2 && N <= 16) gemm_tiles<F32, TM, 1, C3>(M, N, K, loadA, loadB, loadC, storeC);
-  else gemm_tiles<F32, TM, TN, C3>(M, N, K, loadA, loadB, loadC, storeC);
+  if (TN == 2 && N <= 16) gemm_tiles<NT, F32, TM, 1, C3>(M, N, K, loadA, loadB, loadC, storeC);
+  else gemm_tiles<NT, F32, TM, TN, C3>(M, N, K, loadA, loadB, loadC, storeC);
 }
 
 // Inverse of the w x w unit-lower triangle held below the diagonal of L.tri
 // (row-major, tri[i*16+j] = L_ij for i > j), written to L.tinv (zero outside
 // w x w).  Thread j < 16 forward-substitutes column j of L^{-1}.  The caller
 // has synchronised after writing L.tri; this function ends with a barrier.
-__device__ __forceinline__ void tri_inverse_unit_lower(Lds& L, int w) {
+template <class LDS>
+__device__ __forceinline__ void tri_inverse_unit_lower(LDS& L, int w) {
   const int j = threadIdx.x;
   if (j < 16) {
     double2 y[16];
@@ -346,6 +353,21 @@ __device__ __forceinline__ u64 wave_max(u64 x) {
   return umax64(umax64(readlane_u64(x, 0), readlane_u64(x, 16)), umax64(readlane_u64(x, 32), readlane_u64(x, 48)));
 }
 
+// Sum over the wave, returned to every lane (same pattern as wave_max).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  return __longlong_as_double((long long)dpp_u64<CTRL>((u64)__double_as_longlong(x)));
+}
+__device__ __forceinline__ double wave_sum(double x) {
+  x += dpp_f64<0xB1>(x);
+  x += dpp_f64<0x4E>(x);
+  x += dpp_f64<0x141>(x);
+  x += dpp_f64<0x140>(x);
+  const u64 b = (u64)__double_as_longlong(x);
+  return (__longlong_as_double((long long)readlane_u64(b, 0)) + __longlong_as_double((long long)readlane_u64(b, 16))) +
+         (__longlong_as_double((long long)readlane_u64(b, 32)) + __longlong_as_double((long long)readlane_u64(b, 48)));
+}
+
 // Physical row of logical row r of a front whose first s rows are pivoted.
 __device__ __forceinline__ int prow(const int* pm, int s, int r) { return r < s ? pm[r] : r; }
 
@@ -358,8 +380,9 @@ __device__ __forceinline__ int prow(const int* pm, int s, int r) { return r < s 
 // block's earlier panels, factored in registers (rows spread over the
 // threads), and their U rows formed; the rest of the matrix gets one
 // MFMA trailing update per outer block.  Returns true if a zero pivot was met.
-template <int RPT, int NB>
-__device__ __forceinline__ bool tall_lu(Lds& L, double2* FA, int n, int s) {
+template <int RPT, int NB, class LDS>
+__device__ __forceinline__ bool tall_lu(LDS& L, double2* FA, int n, int s) {
+  constexpr int NT = LDS::kNT;
   constexpr int NB2 = 32;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int* pm = L.perm;
@@ -372,7 +395,7 @@ __device__ __forceinline__ bool tall_lu(Lds& L, double2* FA, int n, int s) {
       const int ms = s - k0;         // pivot-eligible panel rows
       // (a) left-looking update of the panel by this block's earlier panels
       if (k0 > K0) {
-        gemm_sub(m, kb, k0 - K0,
+        gemm_sub<NT>(m, kb, k0 - K0,
                  [=](int r, int k) { return FA[(size_t)(K0 + k) * n + prow(pm, s, k0 + r)]; },
                  [=](int k, int c) { return FA[(size_t)(k0 + c) * n + pm[K0 + k]]; },
                  [=](int r, int c) { return FA[(size_t)(k0 + c) * n + prow(pm, s, k0 + r)]; },
@@ -387,7 +410,7 @@ __device__ __forceinline__ bool tall_lu(Lds& L, double2* FA, int n, int s) {
       int lg[RPT];
 #pragma unroll
       for (int q = 0; q < RPT; ++q) {
-        const int rho = tid + kThreads * q;
+        const int rho = tid + NT * q;
         lg[q] = rho;
 #pragma unroll
         for (int j = 0; j < NB; ++j)
@@ -423,7 +446,7 @@ __device__ __forceinline__ bool tall_lu(Lds& L, double2* FA, int n, int s) {
           u64 gk = L.candv[buf][0];
           int pw = 0;                                   // winning wave
   #pragma unroll
-          for (int w = 1; w < kThreads / 64; ++w) {
+          for (int w = 1; w < LDS::kW; ++w) {
             const u64 o = L.candv[buf][w];
             if (o > gk) { gk = o; pw = w; }
           }
@@ -470,14 +493,14 @@ __device__ __forceinline__ bool tall_lu(Lds& L, double2* FA, int n, int s) {
       if (k0 + kb < s) {
         const int cb = k0 + kb;
         if (k0 > K0)
-          gemm_sub(kb, s - cb, k0 - K0,
+          gemm_sub<NT>(kb, s - cb, k0 - K0,
                    [=](int r, int k) { return FA[(size_t)(K0 + k) * n + pm[k0 + r]]; },
                    [=](int k, int c) { return FA[(size_t)(cb + c) * n + pm[K0 + k]]; },
                    [=](int r, int c) { return FA[(size_t)(cb + c) * n + pm[k0 + r]]; },
                    [=](int r, int c, double2 v) { FA[(size_t)(cb + c) * n + pm[k0 + r]] = v; });
         tri_inverse_unit_lower(L, kb);
-        const Lds* LL = &L;
-        gemm_sub(kb, s - cb, kb,
+        const LDS* LL = &L;
+        gemm_sub<NT>(kb, s - cb, kb,
                  [=](int r, int k) { double2 v = LL->tinv[r * 16 + k]; return make_double2(-v.x, -v.y); },
                  [=](int k, int c) { return FA[(size_t)(cb + c) * n + pm[k0 + k]]; },
                  [=](int r, int c) { return zero2(); },
@@ -487,7 +510,7 @@ __device__ __forceinline__ bool tall_lu(Lds& L, double2* FA, int n, int s) {
     }
     // (e) trailing update of rows KE..n, columns KE..s with the block's L and U
     if (KE < s) {
-      gemm_sub(n - KE, s - KE, KE - K0,
+      gemm_sub<NT>(n - KE, s - KE, KE - K0,
                [=](int r, int k) { return FA[(size_t)(K0 + k) * n + prow(pm, s, KE + r)]; },
                [=](int k, int c) { return FA[(size_t)(KE + c) * n + pm[K0 + k]]; },
                [=](int r, int c) { return FA[(size_t)(KE + c) * n + prow(pm, s, KE + r)]; },
@@ -499,28 +522,32 @@ __device__ __forceinline__ bool tall_lu(Lds& L, double2* FA, int n, int s) {
 }
 
 // X L11 = L21 in place (X -> FA rows s..n, columns 0..s); L11 unit lower.
-__device__ __forceinline__ void trsm_right_unit_lower(Lds& L, double2* FA, int n, int s, int b) {
+template <class LDS>
+__device__ __forceinline__ void trsm_right_unit_lower(LDS& L, double2* FA, int n, int s, int b) {
+  constexpr int NT = LDS::kNT;
   const int tid = threadIdx.x;
   const int nblk = (s + 15) / 16;
   for (int J = nblk - 1; J >= 0; --J) {
     const int j0 = 16 * J, j1 = min(s, j0 + 16), w = j1 - j0;
     if (j1 < s) {
       const int* pm = L.perm;
-      gemm_sub(b, w, s - j1,
+      gemm_sub<NT>(b, w, s - j1,
                [=](int r, int k) { return FA[(size_t)(j1 + k) * n + s + r]; },
                [=](int k, int c) { return FA[(size_t)(j0 + c) * n + pm[j1 + k]]; },
                [=](int r, int c) { return FA[(size_t)(j0 + c) * n + s + r]; },
                [=](int r, int c, double2 v) { FA[(size_t)(j0 + c) * n + s + r] = v; });
     }
     {
-      const int i = tid >> 4, jj = tid & 15;
-      L.tri[tid] = (i < w && jj < w) ? FA[(size_t)(j0 + jj) * n + L.perm[j0 + i]] : zero2();
+      for (int t = tid; t < 256; t += NT) {
+        const int i = t >> 4, jj = t & 15;
+        L.tri[t] = (i < w && jj < w) ? FA[(size_t)(j0 + jj) * n + L.perm[j0 + i]] : zero2();
+      }
     }
     __syncthreads();
     tri_inverse_unit_lower(L, w);
     {
-      const Lds* LL = &L;
-      gemm_sub(b, w, w,
+      const LDS* LL = &L;
+      gemm_sub<NT>(b, w, w,
                [=](int r, int k) { return FA[(size_t)(j0 + k) * n + s + r]; },
                [=](int k, int c) { double2 v = LL->tinv[k * 16 + c]; return make_double2(-v.x, -v.y); },
                [=](int r, int c) { return zero2(); },
@@ -530,10 +557,10 @@ __device__ __forceinline__ void trsm_right_unit_lower(Lds& L, double2* FA, int n
   }
 }
 
-template <int RPT, int TC, int CM>
-__global__ __launch_bounds__(kThreads, 3) void k_stage(StageArgs a) {
+template <int RPT, int TC, int CM, int NT, int MAXN>
+__global__ __launch_bounds__(NT, 3) void k_stage(StageArgs a) {
   constexpr int NB = 16 / RPT;  // panel columns held in registers
-  __shared__ Lds L;
+  __shared__ LdsT<NT, MAXN> L;
   const int tid = threadIdx.x;
   const long long total = (long long)a.n_elims * a.nE;
   double2* FA = a.ws + (size_t)blockIdx.x * a.ws_stride;
@@ -543,20 +570,20 @@ __global__ __launch_bounds__(kThreads, 3) void k_stage(StageArgs a) {
     const int s = E.s, b = E.b, n = E.n;
     double2* W = FA + (size_t)n * s;   // FA: tall block n x s; W: b x n
     double2* pool = a.pool + (size_t)e * a.pool_stride;
-    for (int k = tid; k < n; k += kThreads) {
+    for (int k = tid; k < n; k += NT) {
       const int g = a.map_node[E.map + k];
       const int y = g / a.Nx;
       L.node[k] = (y << 16) | (g - y * a.Nx);
       L.srcpos[k] = a.map_srcpos[E.map + k];
     }
-    for (int k = tid; k < s; k += kThreads) L.perm[k] = k;
+    for (int k = tid; k < s; k += NT) L.perm[k] = k;
     __syncthreads();
     const Front fr{L.node, L.srcpos, pool + E.src0, pool + E.src1, E.ld0, E.ld1,
                    Orig{a.H, a.sigma + (size_t)e * 2 * a.Nx * a.Nx, a.sless + (size_t)e * 2 * a.Nx * a.Nx,
                         a.energies[e], a.Nx, a.Ny, a.nst}};
     // 1. assemble the tall block [A_g(S,S); A_g(B,S)]; the other blocks of A_g
     //    and all of Sigma_g are gathered from their sources by the products
-    for_each_rc(n, s, [&](int r, int c) { FA[(size_t)c * n + r] = fr.a(r, c); });
+    for_each_rc<NT>(n, s, [&](int r, int c) { FA[(size_t)c * n + r] = fr.a(r, c); });
     __syncthreads();
     // 2. tall LU, 3. L = L21 L11^{-1}
     if (s > 0) {
@@ -578,13 +605,13 @@ __global__ __launch_bounds__(kThreads, 3) void k_stage(StageArgs a) {
     auto c2 = [=](int r, int c) { return W[(size_t)(s + c) * b + r]; };
     auto s2 = [=](int r, int c, double2 v) { Ro[(size_t)c * b + r] = v; };
     if (E.f32) {
-      gemm_schur<true, TC, CM == 1>(b, b + n, s, l_, b1, c1, s1);
+      gemm_schur<NT, true, TC, CM == 1>(b, b + n, s, l_, b1, c1, s1);
       __syncthreads();
-      gemm_schur<true, TC, CM == 1>(b, b, s, a2, b2, c2, s2);
+      gemm_schur<NT, true, TC, CM == 1>(b, b, s, a2, b2, c2, s2);
     } else {
-      gemm_schur<false, TC, CM == 1>(b, b + n, s, l_, b1, c1, s1);
+      gemm_schur<NT, false, TC, CM == 1>(b, b + n, s, l_, b1, c1, s1);
       __syncthreads();
-      gemm_schur<false, TC, CM == 1>(b, b, s, a2, b2, c2, s2);
+      gemm_schur<NT, false, TC, CM == 1>(b, b, s, a2, b2, c2, s2);
     }
     __syncthreads();
   }
@@ -594,12 +621,13 @@ __global__ __launch_bounds__(kThreads, 3) void k_stage(StageArgs a) {
 // from the Schur complement U_K and its Sigma block R_K, G(K,K) = U_K^{-1} and
 // G<(K,K) = G R_K G^dagger.  G comes out of the same tall LU + L solve as an
 // elimination of [[U_K, I], [I, 0]]: the L block of that elimination is
-// U_K^{-1}.  T = R_K G^dagger is formed once; each requested entry of G< is
-// then a dot product G(i,:) T(:,j).  Outputs are written directly.
-template <int RPT>
-__global__ __launch_bounds__(kThreads, 3) void k_final(StageArgs a, OutArgs o) {
+// U_K^{-1}.  T = R_K G^dagger is formed once on MFMA; each requested entry of
+// G< (the diagonal, and both orders of every bond) is then a dot product
+// G(i,:) T(:,j) computed by one wave.  Outputs are written directly.
+template <int RPT, int NT, int MAXN>
+__global__ __launch_bounds__(NT, 3) void k_final(StageArgs a, OutArgs o) {
   constexpr int NB = 16 / RPT;  // panel columns held in registers
-  __shared__ Lds L;
+  __shared__ LdsT<NT, MAXN> L;
   const int tid = threadIdx.x;
   const long long total = (long long)a.n_elims * a.nE;
   double2* FA = a.ws + (size_t)blockIdx.x * a.ws_stride;
@@ -614,45 +642,55 @@ __global__ __launch_bounds__(kThreads, 3) void k_final(StageArgs a, OutArgs o) {
     const double2* Uin = pool + E.src0;           // U_K, ld bp
     const double2* Rin = Uin + (size_t)bp * bp;   // R_K
     double2* G = pool + E.dst;                    // G(K,K), bp x bp
-    for (int k = tid; k < bp; k += kThreads) L.perm[k] = k;
-    for_each_rc(n, bp, [&](int r, int c) {
+    for (int k = tid; k < bp; k += NT) L.perm[k] = k;
+    for_each_rc<NT>(n, bp, [&](int r, int c) {
       FA[(size_t)c * n + r] = r < bp ? Uin[(size_t)c * bp + r] : make_double2(r - bp == c ? 1.0 : 0.0, 0.0);
     });
     __syncthreads();
     if (tall_lu<RPT, NB>(L, FA, n, bp) && tid == 0) a.status[e] = 1;
     trsm_right_unit_lower(L, FA, n, bp, bp);
     // G(:, perm[k]) = L(:, k)
-    for_each_rc(bp, bp, [&](int i, int k) { G[(size_t)L.perm[k] * bp + i] = FA[(size_t)k * n + bp + i]; });
+    for_each_rc<NT>(bp, bp, [&](int i, int k) { G[(size_t)L.perm[k] * bp + i] = FA[(size_t)k * n + bp + i]; });
     __syncthreads();
     // T = R_K G^dagger   (gemm_sub returns 0 - R G^dagger)
-    gemm_sub(bp, bp, bp,
+    gemm_sub<NT>(bp, bp, bp,
              [=](int r, int k) { return Rin[(size_t)k * bp + r]; },
              [=](int k, int c) { return conjd(G[(size_t)k * bp + c]); },
              [=](int r, int c) { return zero2(); },
              [=](int r, int c, double2 v) { T[(size_t)c * bp + r] = make_double2(-v.x, -v.y); });
     __syncthreads();
-    // G< = G T (the requested entries are read from it below)
-    double2* GL = T + (size_t)bp * bp;
-    gemm_sub(bp, bp, bp,
-             [=](int r, int k) { return G[(size_t)k * bp + r]; },
-             [=](int k, int c) { const double2 v = T[(size_t)c * bp + k]; return make_double2(-v.x, -v.y); },
-             [=](int r, int c) { return zero2(); },
-             [=](int r, int c, double2 v) { GL[(size_t)c * bp + r] = v; });
-    __syncthreads();
-    auto gless = [&](int i, int j) { return GL[(size_t)j * bp + i]; };
-    for (int k = tid; k < Lo.n_nodes; k += kThreads) {
-      const int node = o.outnode[2 * (Lo.node_first + k)];
-      const int l = o.outnode[2 * (Lo.node_first + k) + 1];
-      o.diag_G[e * nn + node] = G[(size_t)l * bp + l];
-      o.diag_Gless[e * nn + node] = gless(l, l);
+    // requested entries of G< = G T, one wave per entry: lanes split k, DPP sum
+    const int lane = tid & 63, wave = tid >> 6;
+    auto gless = [&](int i, int j) {
+      double re = 0.0, im = 0.0;
+      for (int k = lane; k < bp; k += 64) {
+        const double2 p = cmul(G[(size_t)k * bp + i], T[(size_t)j * bp + k]);
+        re += p.x; im += p.y;
+      }
+      return make_double2(wave_sum(re), wave_sum(im));
+    };
+    for (int q = wave; q < Lo.n_nodes; q += NT / 64) {
+      const int node = o.outnode[2 * (Lo.node_first + q)];
+      const int l = o.outnode[2 * (Lo.node_first + q) + 1];
+      const double2 gl = gless(l, l);
+      if (lane == 0) {
+        o.diag_G[e * nn + node] = G[(size_t)l * bp + l];
+        o.diag_Gless[e * nn + node] = gl;
+      }
     }
-    for (int k = tid; k < Lo.n_bonds; k += kThreads) {
-      const int* ob = o.outbond + 5 * (Lo.bond_first + k);
+    for (int q = wave; q < Lo.n_bonds; q += NT / 64) {
+      const int* ob = o.outbond + 5 * (Lo.bond_first + q);
       const int bond = ob[0], li = ob[1], lj = ob[2], kk = ob[3], hf = ob[4];
       const size_t oi = (size_t)e * o.n_bonds + bond;
-      if (o.bond_G) o.bond_G[oi] = G[(size_t)lj * bp + li];
-      if (o.bond_Gless) o.bond_Gless[oi] = gless(li, lj);
-      if (o.bond_J) o.bond_J[oi] = 2.0 * o.H[(size_t)kk * nn + hf] * gless(lj, li).x;
+      if (o.bond_Gless) {
+        const double2 v = gless(li, lj);
+        if (lane == 0) o.bond_Gless[oi] = v;
+      }
+      if (o.bond_J) {
+        const double2 v = gless(lj, li);
+        if (lane == 0) o.bond_J[oi] = 2.0 * o.H[(size_t)kk * nn + hf] * v.x;
+      }
+      if (o.bond_G && lane == 0) o.bond_G[oi] = G[(size_t)lj * bp + li];
     }
     __syncthreads();
   }
@@ -662,11 +700,11 @@ __global__ __launch_bounds__(kThreads, 3) void k_final(StageArgs a, OutArgs o) {
 #error "kernels.hip is compiled once per kernel family: -DFIND_TU=1, 2, 3 or 4"
 #endif
 // Launchers.  The source is compiled once per kernel family (FIND_TU = 1:
-// k_stage with 1 panel row per thread, 2: with 2, 3: with 4 and 8, 4: k_final)
-// so that the families build in parallel.
+// k_stage with 1 panel row per thread, 2: with 2, 3: with 4 and 8 and the
+// one-wave-per-front forms, 4: k_final) so that the families build in parallel.
 #define FIND_LAUNCH_STAGE(R, T, C)                                                            \
   if (tc == T && cm == C) {                                                                   \
-    hipLaunchKernelGGL((k_stage<R, T, C>), dim3(grid), dim3(kThreads), 0, st, a);             \
+    hipLaunchKernelGGL((k_stage<R, T, C, kThreads, kMaxFront>), dim3(grid), dim3(kThreads), 0, st, a); \
     return hipGetLastError();                                                                 \
   }
 #if FIND_TU == 1 || FIND_TU == 2
@@ -682,14 +720,33 @@ hipError_t launch_stage_r48(const StageArgs& a, int rpt, int tc, int cm, int gri
   if (rpt == 8) { FIND_LAUNCH_STAGE(8, 0, 0) FIND_LAUNCH_STAGE(8, 0, 1) }
   return hipErrorInvalidValue;
 }
+// one wave per front (fronts of at most kWaveMaxFront nodes)
+hipError_t launch_stage_w(const StageArgs& a, int rpt, int cm, int grid, hipStream_t st) {
+#define FIND_LAUNCH_W(R, C)                                                                    \
+  if (rpt == R && cm == C) {                                                                  \
+    hipLaunchKernelGGL((k_stage<R, 0, C, 64, kWaveMaxFront>), dim3(grid), dim3(64), 0, st, a); \
+    return hipGetLastError();                                                                 \
+  }
+  FIND_LAUNCH_W(1, 0) FIND_LAUNCH_W(2, 0) FIND_LAUNCH_W(1, 1) FIND_LAUNCH_W(2, 1)
+#undef FIND_LAUNCH_W
+  return hipErrorInvalidValue;
+}
 #endif
 #if FIND_TU == 4
 hipError_t launch_final(const StageArgs& a, const OutArgs& o, int rpt, int grid, hipStream_t st) {
   switch (rpt) {
-    case 1: hipLaunchKernelGGL(k_final<1>, dim3(grid), dim3(kThreads), 0, st, a, o); break;
-    case 2: hipLaunchKernelGGL(k_final<2>, dim3(grid), dim3(kThreads), 0, st, a, o); break;
-    case 4: hipLaunchKernelGGL(k_final<4>, dim3(grid), dim3(kThreads), 0, st, a, o); break;
-    case 8: hipLaunchKernelGGL(k_final<8>, dim3(grid), dim3(kThreads), 0, st, a, o); break;
+    case 1: hipLaunchKernelGGL((k_final<1, kThreads, kMaxFront>), dim3(grid), dim3(kThreads), 0, st, a, o); break;
+    case 2: hipLaunchKernelGGL((k_final<2, kThreads, kMaxFront>), dim3(grid), dim3(kThreads), 0, st, a, o); break;
+    case 4: hipLaunchKernelGGL((k_final<4, kThreads, kMaxFront>), dim3(grid), dim3(kThreads), 0, st, a, o); break;
+    case 8: hipLaunchKernelGGL((k_final<8, kThreads, kMaxFront>), dim3(grid), dim3(kThreads), 0, st, a, o); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+hipError_t launch_final_w(const StageArgs& a, const OutArgs& o, int rpt, int grid, hipStream_t st) {
+  switch (rpt) {
+    case 1: hipLaunchKernelGGL((k_final<1, 64, kWaveMaxFront>), dim3(grid), dim3(64), 0, st, a, o); break;
+    case 2: hipLaunchKernelGGL((k_final<2, 64, kWaveMaxFront>), dim3(grid), dim3(64), 0, st, a, o); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

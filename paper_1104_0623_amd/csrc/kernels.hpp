@@ -56,23 +56,41 @@ constexpr int kMaxFront = 2048;
 constexpr int kThreads = 256;
 
 // Stage launchers (one per kernel family; see kernels.hip).  tc: wave tile of
-// the Schur products (0..kTileConfigs-1; families with 4 or 8 panel rows per
-// thread take tc = 0 only), cm: 0 = 4M, 1 = 3M complex products.
-constexpr int kTileConfigs = 4;
+// the Schur products (0..3; families with 4 or 8 panel rows per thread take
+// tc = 0 only) or kTileWave: one 64-thread workgroup (a single wave) per front,
+// for stages whose fronts have at most kWaveMaxFront nodes.  cm: 0 = 4M,
+// 1 = 3M complex products.
+constexpr int kTileConfigs = 5;
+constexpr int kTileWave = 4;
+constexpr int kWaveMaxFront = 128;
+constexpr int kWaveGroupsPerSlot = 4;   // 64-thread groups resident where one 256-thread group is
 #define FIND_CAT_(a, b) a##b
 #define FIND_CAT(a, b) FIND_CAT_(a, b)
 hipError_t launch_stage_r1(const StageArgs& a, int tc, int cm, int grid, hipStream_t st);
 hipError_t launch_stage_r2(const StageArgs& a, int tc, int cm, int grid, hipStream_t st);
 hipError_t launch_stage_r48(const StageArgs& a, int rpt, int tc, int cm, int grid, hipStream_t st);
+hipError_t launch_stage_w(const StageArgs& a, int rpt, int cm, int grid, hipStream_t st);
 hipError_t launch_final(const StageArgs& a, const OutArgs& o, int rpt, int grid, hipStream_t st);
-// tile configurations available to a stage whose fronts need rpt panel rows per thread
-inline int stage_tile_configs(int rpt) { return rpt <= 2 ? kTileConfigs : 1; }
-inline hipError_t launch_stage(const StageArgs& a, int rpt, int tc, int cm, int grid, hipStream_t st) {
-  switch (rpt) {
+hipError_t launch_final_w(const StageArgs& a, const OutArgs& o, int rpt, int grid, hipStream_t st);
+// panel rows per lane of the one-wave form
+inline int wave_rpt(int n) { return n <= 64 ? 1 : 2; }
+// bit mask of the tile configurations a stage with fronts of at most maxn nodes has
+inline int stage_tile_mask(int maxn, bool final_stage) {
+  int m = final_stage ? 1 : (panel_rpt(maxn) <= 2 ? 0xf : 1);
+  if (maxn <= kWaveMaxFront) m |= 1 << kTileWave;
+  return m;
+}
+inline hipError_t launch_stage(const StageArgs& a, int maxn, int tc, int cm, int grid, hipStream_t st) {
+  if (tc == kTileWave) return maxn <= kWaveMaxFront ? launch_stage_w(a, wave_rpt(maxn), cm, grid, st) : hipErrorInvalidValue;
+  switch (panel_rpt(maxn)) {
     case 1: return launch_stage_r1(a, tc, cm, grid, st);
     case 2: return launch_stage_r2(a, tc, cm, grid, st);
-    default: return launch_stage_r48(a, rpt, tc, cm, grid, st);
+    default: return launch_stage_r48(a, panel_rpt(maxn), tc, cm, grid, st);
   }
+}
+inline hipError_t launch_final_tc(const StageArgs& a, const OutArgs& o, int maxn, int tc, int grid, hipStream_t st) {
+  if (tc == kTileWave) return maxn <= kWaveMaxFront ? launch_final_w(a, o, wave_rpt(maxn), grid, st) : hipErrorInvalidValue;
+  return tc == 0 ? launch_final(a, o, panel_rpt(maxn), grid, st) : hipErrorInvalidValue;
 }
 
 }  // namespace findmi

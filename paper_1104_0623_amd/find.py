@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libfind.so")
 FIND_OK, FIND_E_ARG, FIND_E_NOMEM, FIND_E_SINGULAR, FIND_E_DEVICE, FIND_E_UNSUPPORTED = range(6)
 PREC_FP64, PREC_MIXED = 0, 1
 CPLX_4M, CPLX_3M = 0, 1
-TILE_NAMES = ("32x32", "32x16", "16x32", "16x16")
+TILE_NAMES = ("32x32", "32x16", "16x32", "16x16", "wave")
 EF_FIELDS, SF_FIELDS, LF_FIELDS, ON_FIELDS, OB_FIELDS = 13, 4, 6, 2, 5
 EXPORTED = ["find_plan_create", "find_plan_destroy", "find_plan_footprint", "find_plan_flops",
             "find_n_bonds", "find_solve", "find_sync_status", "find_last_error",
@@ -80,7 +80,7 @@ def lib() -> ctypes.CDLL:
                                         ctypes.POINTER(ctypes.c_int)]
         L.find_plan_profile.restype = st
         L.find_plan_autotune.argtypes = [vp, i32] + [vp] * 6 + [i32, vp]; L.find_plan_autotune.restype = st
-        L.find_plan_get_tiles.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_int)]
+        L.find_plan_get_tiles.argtypes = [vp, vp, vp, i32, ctypes.POINTER(ctypes.c_int)]
         L.find_plan_get_tiles.restype = st
         L.find_plan_set_tiles.argtypes = [vp, vp, i32]; L.find_plan_set_tiles.restype = st
         _lib = L
@@ -159,12 +159,20 @@ class Plan:
         return ms.value, fl.value, n.value
 
     def tiles(self) -> list[int]:
-        """Wave-tile configuration of each stage (index into TILE_NAMES)."""
+        """Launch configuration of each stage (index into TILE_NAMES)."""
         n = ctypes.c_int()
-        _check(lib().find_plan_get_tiles(self._h, None, 0, ctypes.byref(n)))
+        _check(lib().find_plan_get_tiles(self._h, None, None, 0, ctypes.byref(n)))
         buf = (ctypes.c_int * max(1, n.value))()
-        _check(lib().find_plan_get_tiles(self._h, buf, n.value, ctypes.byref(n)))
+        _check(lib().find_plan_get_tiles(self._h, buf, None, n.value, ctypes.byref(n)))
         return list(buf[: n.value])
+
+    def tile_options(self) -> list[list[int]]:
+        """Configurations each stage has."""
+        n = ctypes.c_int()
+        _check(lib().find_plan_get_tiles(self._h, None, None, 0, ctypes.byref(n)))
+        buf = (ctypes.c_int * max(1, n.value))()
+        _check(lib().find_plan_get_tiles(self._h, None, buf, n.value, ctypes.byref(n)))
+        return [[t for t in range(len(TILE_NAMES)) if m >> t & 1] for m in buf[: n.value]]
 
     def set_tiles(self, tiles) -> None:
         buf = (ctypes.c_int * max(1, len(tiles)))(*tiles)

@@ -126,18 +126,26 @@ def test_singleton_and_one_leaf_meshes():
 
 
 def test_tile_configurations_give_bitwise_equal_results():
-    """The wave tile of the Schur products only moves work between waves."""
+    """Wave tiles only move work between waves (bitwise equal results); the
+    one-wave form may round differently."""
     f = find()
     E = inputs.energies_linspace(-3.2, 3.1, 5)
     prob = inputs.make_problem(40, 52, 9, vmax=1.0, seed=7, energies=E, fL=1.0, fR=0.2)
     plan = f.Plan(40, 52, 9)
     base = f.run_problem(plan, prob, want_bonds=True)
-    stages = plan.export()["stages"]
-    for tc in (1, 2, 3):
-        plan.set_tiles([0 if st[2] == 3 else tc for st in stages])
+    opts = plan.tile_options()
+    assert any(4 in o for o in opts)     # the small-front stages have the one-wave form
+    for tc in (1, 2, 3, 4):
+        plan.set_tiles([tc if tc in o else 0 for o in opts])
         out = f.run_problem(plan, prob, want_bonds=True)
         for k in base:
-            assert np.array_equal(out[k], base[k]), (tc, k)
+            if tc < 4:
+                assert np.array_equal(out[k], base[k]), (tc, k)
+            else:
+                # the one-wave form factors fronts of 65..128 nodes with 8-column
+                # register panels instead of 16: same operations, other rounding
+                for e in range(E.size):
+                    assert nrel(out[k][e], base[k][e]) <= TOL / 10, (tc, k, e)
 
 
 def test_autotune_picks_valid_tiles_and_keeps_results():
@@ -153,15 +161,16 @@ def test_autotune_picks_valid_tiles_and_keeps_results():
     dG = torch.zeros((nE, 64, 64), dtype=torch.complex128, device=dev)
     dL = torch.zeros_like(dG)
     tiles = f.autotune(plan, t["energies"], t["H"], t["sigma"], t["sigma_less"], dG, dL, reps=1)
-    stages = plan.export()["stages"]
-    assert len(tiles) == len(stages)
-    assert all(0 <= tc < (1 if st[2] == 3 else 4) for tc, st in zip(tiles, stages))
-    # the tuning pass leaves its (bitwise identical) results in the outputs
-    assert np.array_equal(dG.cpu().numpy(), base["diag_G"])
-    assert np.array_equal(dL.cpu().numpy(), base["diag_Gless"])
+    opts = plan.tile_options()
+    assert len(tiles) == len(opts)
+    assert all(tc in o for tc, o in zip(tiles, opts))
+    # the tuning pass leaves the results of a solve with the chosen tiles
     again = f.run_problem(plan, prob, want_bonds=False)
+    assert np.array_equal(dG.cpu().numpy(), again["diag_G"])
+    assert np.array_equal(dL.cpu().numpy(), again["diag_Gless"])
     for k in again:
-        assert np.array_equal(again[k], base[k]), k
+        for e in range(nE):
+            assert nrel(again[k][e], base[k][e]) <= TOL / 10, (k, e)
 
 
 @pytest.mark.parametrize("Nx,Ny,stencil,leaf", [(16, 16, 5, 4), (33, 20, 9, 8), (1, 11, 5, 2), (24, 40, 5, 8)])

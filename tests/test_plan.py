@@ -56,23 +56,31 @@ def test_tile_and_complex_mode_options():
     assert ei.value.status == find.FIND_E_ARG
     plan = find.Plan(64, 64, 5, complex_mode=find.CPLX_3M)
     n = plan.summary()["n_stages"]
-    tiles = plan.tiles()
-    assert tiles == [0] * n
-    stages = plan.export()["stages"]
-    # every Schur stage of a mesh whose fronts stay <= 512 has all four
-    # configurations; the final leaf-block stages have only configuration 0
-    want = [0 if st[2] == 3 else 3 for st in stages]
-    plan.set_tiles(want)
-    assert plan.tiles() == want
-    bad = list(want)
-    bad[[k for k, st in enumerate(stages) if st[2] == 3][0]] = 1
+    assert plan.tiles() == [0] * n
+    ex = plan.export()
+    stages, elims = ex["stages"], ex["elims"]
+    opts = plan.tile_options()
+    assert len(opts) == n
+    for st, o in zip(stages, opts):
+        maxn = int(elims[st[0]:st[0] + st[1], 3].max())
+        final = st[2] == 3
+        # Schur stages whose fronts stay <= 512 have the four wave tiles; the
+        # final leaf blocks only the default; fronts <= 128 also the one-wave form
+        want = ([0] if final else [0, 1, 2, 3]) + ([4] if maxn <= 128 else [])
+        assert o == want, (st, maxn, o)
+    pick = [o[-1] for o in opts]
+    plan.set_tiles(pick)
+    assert plan.tiles() == pick
+    bad = list(pick)
+    k = [i for i, o in enumerate(opts) if 1 not in o][0]
+    bad[k] = 1
     with pytest.raises(find.FindError):
         plan.set_tiles(bad)
     with pytest.raises(find.FindError):
-        plan.set_tiles(want[:-1])
+        plan.set_tiles(pick[:-1])
     with pytest.raises(find.FindError):
-        plan.set_tiles([4] * n)
-    assert plan.tiles() == want          # a rejected call changes nothing
+        plan.set_tiles([5] * n)
+    assert plan.tiles() == pick          # a rejected call changes nothing
     L = find.lib()
     assert L.find_plan_autotune(None, 1, *([None] * 6), 2, None) == find.FIND_E_ARG
     assert L.find_plan_autotune(plan.handle, 0, *([None] * 6), 2, None) == find.FIND_E_ARG

@@ -26,9 +26,9 @@ PEAK = {"fp64": 78.6, "mixed": 157.3}   # MI355X dense MFMA TFLOP/s (FP64, FP32)
 # solve, from rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs (calibrated on a
 # plain copy; profiles/elim_kernels_c3_128x128_fp64.md).  Valid only for the
 # kernel source they were measured on.
-TRAFFIC_BYTES_PER_LAUNCH = 52613313824.2
-TRAFFIC_KERNEL_SHA = "c8d437d96e7b26a3"
-TRAFFIC_TILES = "33110000000000011000"
+TRAFFIC_BYTES_PER_LAUNCH = 53506903066.6
+TRAFFIC_KERNEL_SHA = "72ab5654a4defe17"
+TRAFFIC_TILES = "44410000300000011000"
 
 
 def measured_traffic(preset: str, precision: str, tiles: str, cmode: str):

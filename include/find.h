@@ -166,7 +166,8 @@ find_status find_plan_profile(find_plan plan, double* kernel_ms, double* kernel_
  * tiles of 32x32, 32x16, 16x32 or 16x16 for the Schur products of eq.
  * (major-update) and eq. (gless-update-rule) (stages whose fronts exceed 512
  * nodes, and the final leaf blocks, have 0 only); 4 = one 64-thread workgroup
- * (a single wave) per front, for stages whose fronts have at most 128 nodes.
+ * (a single wave) per front, for stages whose fronts have at most 128 nodes;
+ * 5 = one 128-thread workgroup (two waves) per front, fronts of at most 256.
  * A configuration only decides which threads compute which part of the same
  * operations in the same order, so results are bitwise the same for every
  * configuration.

@@ -199,10 +199,12 @@ find_status ensure_device(find_plan_s* p, DevState** out) {
   return FIND_OK;
 }
 
-// Workgroups a stage may launch: one per slot, or kWaveGroupsPerSlot 64-thread
-// groups per slot when its fronts are small enough for the one-wave form.
+// Workgroups a stage may launch at most: one per slot, or several smaller
+// workgroups per slot when its fronts allow the one- or two-wave form.
 long long stage_groups(const DevState& d, const DevStage& s) {
-  return (long long)d.slots * (s.maxn <= kWaveMaxFront ? kWaveGroupsPerSlot : 1);
+  const int g = s.maxn <= kWaveMaxFront ? groups_per_slot(kTileWave)
+              : s.maxn <= kTwoWaveMaxFront ? groups_per_slot(kTileTwoWave) : 1;
+  return (long long)d.slots * g;
 }
 
 // Workspace (complex elements) for passes of ec energies: every stage needs
@@ -444,7 +446,7 @@ hipError_t launch_stage_k(const find_plan_s* plan, const DevState* d, int k, Sta
   const DevStage& s2 = d->stages[k];
   a.elims = s2.d_elims; a.n_elims = s2.count; a.ws_stride = s2.ws_stride;
   const long long items = (long long)s2.count * a.nE;
-  const long long groups = tc == kTileWave ? stage_groups(*d, s2) : d->slots;
+  const long long groups = (long long)d->slots * groups_per_slot(tc);
   const int grid = int(std::min<long long>(items, groups));
   if (grid < 1) return hipSuccess;
   if (s2.phase == PH_FINAL) return launch_final_tc(a, o, s2.maxn, tc, grid, st);

@@ -731,6 +731,17 @@ hipError_t launch_stage_w(const StageArgs& a, int rpt, int cm, int grid, hipStre
 #undef FIND_LAUNCH_W
   return hipErrorInvalidValue;
 }
+// two waves per front (fronts of at most kTwoWaveMaxFront nodes)
+hipError_t launch_stage_w2(const StageArgs& a, int rpt, int cm, int grid, hipStream_t st) {
+#define FIND_LAUNCH_W2(R, C)                                                                   \
+  if (rpt == R && cm == C) {                                                                  \
+    hipLaunchKernelGGL((k_stage<R, 0, C, 128, kTwoWaveMaxFront>), dim3(grid), dim3(128), 0, st, a); \
+    return hipGetLastError();                                                                 \
+  }
+  FIND_LAUNCH_W2(1, 0) FIND_LAUNCH_W2(2, 0) FIND_LAUNCH_W2(1, 1) FIND_LAUNCH_W2(2, 1)
+#undef FIND_LAUNCH_W2
+  return hipErrorInvalidValue;
+}
 #endif
 #if FIND_TU == 4
 hipError_t launch_final(const StageArgs& a, const OutArgs& o, int rpt, int grid, hipStream_t st) {
@@ -739,6 +750,14 @@ hipError_t launch_final(const StageArgs& a, const OutArgs& o, int rpt, int grid,
     case 2: hipLaunchKernelGGL((k_final<2, kThreads, kMaxFront>), dim3(grid), dim3(kThreads), 0, st, a, o); break;
     case 4: hipLaunchKernelGGL((k_final<4, kThreads, kMaxFront>), dim3(grid), dim3(kThreads), 0, st, a, o); break;
     case 8: hipLaunchKernelGGL((k_final<8, kThreads, kMaxFront>), dim3(grid), dim3(kThreads), 0, st, a, o); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+hipError_t launch_final_w2(const StageArgs& a, const OutArgs& o, int rpt, int grid, hipStream_t st) {
+  switch (rpt) {
+    case 1: hipLaunchKernelGGL((k_final<1, 128, kTwoWaveMaxFront>), dim3(grid), dim3(128), 0, st, a, o); break;
+    case 2: hipLaunchKernelGGL((k_final<2, 128, kTwoWaveMaxFront>), dim3(grid), dim3(128), 0, st, a, o); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -57,31 +57,41 @@ constexpr int kThreads = 256;
 
 // Stage launchers (one per kernel family; see kernels.hip).  tc: wave tile of
 // the Schur products (0..3; families with 4 or 8 panel rows per thread take
-// tc = 0 only) or kTileWave: one 64-thread workgroup (a single wave) per front,
-// for stages whose fronts have at most kWaveMaxFront nodes.  cm: 0 = 4M,
-// 1 = 3M complex products.
-constexpr int kTileConfigs = 5;
-constexpr int kTileWave = 4;
+// tc = 0 only), kTileWave: one 64-thread workgroup (a single wave) per front,
+// for stages whose fronts have at most kWaveMaxFront nodes, or kTileTwoWave:
+// one 128-thread workgroup per front (fronts of at most kTwoWaveMaxFront
+// nodes).  cm: 0 = 4M, 1 = 3M complex products.
+constexpr int kTileConfigs = 6;
+constexpr int kTileWave = 4;       // one wave (64 threads) per front
+constexpr int kTileTwoWave = 5;    // two waves (128 threads) per front
 constexpr int kWaveMaxFront = 128;
-constexpr int kWaveGroupsPerSlot = 4;   // 64-thread groups resident where one 256-thread group is
+constexpr int kTwoWaveMaxFront = 256;
+// workgroups resident where one 256-thread workgroup is, for a configuration
+inline int groups_per_slot(int tc) { return tc == kTileWave ? 4 : tc == kTileTwoWave ? 2 : 1; }
 #define FIND_CAT_(a, b) a##b
 #define FIND_CAT(a, b) FIND_CAT_(a, b)
 hipError_t launch_stage_r1(const StageArgs& a, int tc, int cm, int grid, hipStream_t st);
 hipError_t launch_stage_r2(const StageArgs& a, int tc, int cm, int grid, hipStream_t st);
 hipError_t launch_stage_r48(const StageArgs& a, int rpt, int tc, int cm, int grid, hipStream_t st);
 hipError_t launch_stage_w(const StageArgs& a, int rpt, int cm, int grid, hipStream_t st);
+hipError_t launch_stage_w2(const StageArgs& a, int rpt, int cm, int grid, hipStream_t st);
 hipError_t launch_final(const StageArgs& a, const OutArgs& o, int rpt, int grid, hipStream_t st);
 hipError_t launch_final_w(const StageArgs& a, const OutArgs& o, int rpt, int grid, hipStream_t st);
-// panel rows per lane of the one-wave form
+hipError_t launch_final_w2(const StageArgs& a, const OutArgs& o, int rpt, int grid, hipStream_t st);
+// panel rows per thread of the one- and two-wave forms
 inline int wave_rpt(int n) { return n <= 64 ? 1 : 2; }
+inline int wave2_rpt(int n) { return n <= 128 ? 1 : 2; }
 // bit mask of the tile configurations a stage with fronts of at most maxn nodes has
 inline int stage_tile_mask(int maxn, bool final_stage) {
   int m = final_stage ? 1 : (panel_rpt(maxn) <= 2 ? 0xf : 1);
   if (maxn <= kWaveMaxFront) m |= 1 << kTileWave;
+  if (maxn <= kTwoWaveMaxFront) m |= 1 << kTileTwoWave;
   return m;
 }
 inline hipError_t launch_stage(const StageArgs& a, int maxn, int tc, int cm, int grid, hipStream_t st) {
   if (tc == kTileWave) return maxn <= kWaveMaxFront ? launch_stage_w(a, wave_rpt(maxn), cm, grid, st) : hipErrorInvalidValue;
+  if (tc == kTileTwoWave)
+    return maxn <= kTwoWaveMaxFront ? launch_stage_w2(a, wave2_rpt(maxn), cm, grid, st) : hipErrorInvalidValue;
   switch (panel_rpt(maxn)) {
     case 1: return launch_stage_r1(a, tc, cm, grid, st);
     case 2: return launch_stage_r2(a, tc, cm, grid, st);
@@ -90,6 +100,8 @@ inline hipError_t launch_stage(const StageArgs& a, int maxn, int tc, int cm, int
 }
 inline hipError_t launch_final_tc(const StageArgs& a, const OutArgs& o, int maxn, int tc, int grid, hipStream_t st) {
   if (tc == kTileWave) return maxn <= kWaveMaxFront ? launch_final_w(a, o, wave_rpt(maxn), grid, st) : hipErrorInvalidValue;
+  if (tc == kTileTwoWave)
+    return maxn <= kTwoWaveMaxFront ? launch_final_w2(a, o, wave2_rpt(maxn), grid, st) : hipErrorInvalidValue;
   return tc == 0 ? launch_final(a, o, panel_rpt(maxn), grid, st) : hipErrorInvalidValue;
 }
 

@@ -135,15 +135,16 @@ def test_tile_configurations_give_bitwise_equal_results():
     base = f.run_problem(plan, prob, want_bonds=True)
     opts = plan.tile_options()
     assert any(4 in o for o in opts)     # the small-front stages have the one-wave form
-    for tc in (1, 2, 3, 4):
+    for tc in (1, 2, 3, 4, 5):
         plan.set_tiles([tc if tc in o else 0 for o in opts])
         out = f.run_problem(plan, prob, want_bonds=True)
         for k in base:
             if tc < 4:
                 assert np.array_equal(out[k], base[k]), (tc, k)
             else:
-                # the one-wave form factors fronts of 65..128 nodes with 8-column
-                # register panels instead of 16: same operations, other rounding
+                # the one- and two-wave forms factor fronts of 65..128 (129..256)
+                # nodes with 8-column register panels instead of 16: same
+                # operations, other rounding
                 for e in range(E.size):
                     assert nrel(out[k][e], base[k][e]) <= TOL / 10, (tc, k, e)
 

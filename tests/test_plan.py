@@ -66,7 +66,7 @@ def test_tile_and_complex_mode_options():
         final = st[2] == 3
         # Schur stages whose fronts stay <= 512 have the four wave tiles; the
         # final leaf blocks only the default; fronts <= 128 also the one-wave form
-        want = ([0] if final else [0, 1, 2, 3]) + ([4] if maxn <= 128 else [])
+        want = ([0] if final else [0, 1, 2, 3]) + ([4] if maxn <= 128 else []) + ([5] if maxn <= 256 else [])
         assert o == want, (st, maxn, o)
     pick = [o[-1] for o in opts]
     plan.set_tiles(pick)
@@ -79,7 +79,7 @@ def test_tile_and_complex_mode_options():
     with pytest.raises(find.FindError):
         plan.set_tiles(pick[:-1])
     with pytest.raises(find.FindError):
-        plan.set_tiles([5] * n)
+        plan.set_tiles([6] * n)
     assert plan.tiles() == pick          # a rejected call changes nothing
     L = find.lib()
     assert L.find_plan_autotune(None, 1, *([None] * 6), 2, None) == find.FIND_E_ARG

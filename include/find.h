@@ -87,7 +87,16 @@ typedef enum { FIND_CPLX_4M = 0, FIND_CPLX_3M = 1 } find_complex_mode;
  *                 complex product) or FIND_CPLX_3M (three: ar br, ai bi and
  *                 (ar + ai)(br + bi)).  3M rounds differently, within the
  *                 same tolerances; flop counts stay at 8 per complex
- *                 multiply-add either way. */
+ *                 multiply-add either way.
+ *   symmetric     1 asserts that A is complex symmetric (H real symmetric,
+ *                 Sigma_L and Sigma_R complex symmetric, as for leads with a
+ *                 real transverse basis) and Sigma< anti-Hermitian.  Every
+ *                 Schur complement U is then complex symmetric (Prop. 1 of
+ *                 the paper) and every R anti-Hermitian, so only their lower
+ *                 triangles are formed and the upper triangles are mirrored
+ *                 (s b^2 fewer complex multiply-adds per elimination; the
+ *                 flop model of find_plan_flops follows).  Inputs that break
+ *                 the assertion give wrong results.  0 (default) = general. */
 typedef struct {
   int leaf;
   int precision;
@@ -95,7 +104,8 @@ typedef struct {
   int fp64_top_levels;
   size_t workspace_budget;
   int complex_mode;
-  int reserved[7];
+  int symmetric;
+  int reserved[6];
 } find_plan_opts;
 
 /* Build the cluster tree, boundary sets, gather maps and level schedule for

@@ -144,7 +144,7 @@ find_status ensure_device(find_plan_s* p, DevState** out) {
       d.f32 = (p->opts.precision == FIND_PREC_MIXED && e.kind == K_SCHUR && e.level > top && e.s < 512) ? 1 : 0;
       maxn = std::max(maxn, e.n);
       ds_st.maxb = std::max(ds_st.maxb, e.b);
-      ds_st.flops_per_energy += elim_flops(e);
+      ds_st.flops_per_energy += elim_flops(e, p->opts.symmetric != 0);
       const long long need = e.kind == K_FINAL ? 3LL * e.b * e.b                     // [U; I] and T
                                                : (long long)e.n * e.s + (long long)e.b * e.n;  // tall block and W
       ds_st.ws_stride = std::max<long long>(ds_st.ws_stride, need);
@@ -257,6 +257,7 @@ find_status find_plan_create(int Nx, int Ny, int stencil, const find_plan_opts* 
   if (o.max_energies < 0) return fail(FIND_E_ARG, "find_plan_create: max_energies must be >= 0");
   if (o.complex_mode != FIND_CPLX_4M && o.complex_mode != FIND_CPLX_3M)
     return fail(FIND_E_ARG, "find_plan_create: unknown complex_mode");
+  if (o.symmetric != 0 && o.symmetric != 1) return fail(FIND_E_ARG, "find_plan_create: symmetric must be 0 or 1");
   if ((long long)Nx * Ny > (1LL << 24)) return fail(FIND_E_UNSUPPORTED, "find_plan_create: mesh larger than 2^24 nodes");
   find_plan_s* p = new (std::nothrow) find_plan_s();
   if (!p) return fail(FIND_E_NOMEM, "find_plan_create: host allocation failed");
@@ -342,7 +343,7 @@ find_status find_plan_export(find_plan plan, int32_t* elims, int32_t* maps, int3
 
 find_status find_plan_flops(find_plan plan, int want_bonds, double* flops_per_energy) {
   if (!plan || !flops_per_energy) return fail(FIND_E_ARG, "find_plan_flops: NULL argument");
-  *flops_per_energy = plan->P.flops[want_bonds ? 1 : 0];
+  *flops_per_energy = plan->P.flops[plan->opts.symmetric ? 1 : 0][want_bonds ? 1 : 0];
   return FIND_OK;
 }
 
@@ -427,6 +428,7 @@ void pass_args(const find_plan_s* plan, const DevState* d, int variant, int e0, 
   a.ws = d->ws;
   a.Nx = P.Nx; a.Ny = P.Ny; a.nst = P.stencil == 9 ? 5 : 3;
   a.status = d->status + e0;
+  a.sym = plan->opts.symmetric;
   OutArgs o{};
   o.leaves = d->d_leafout[variant];
   o.outnode = d->d_outnode; o.outbond = d->d_outbond; o.H = H;

@@ -116,6 +116,7 @@ struct Front {
   const double2* U1;
   int ld0, ld1;
   Orig o;
+  int sym;             // sources hold only the lower triangle of U (= U^T) and R (= -R^dagger)
 
   __device__ double2 a(int r, int c) const {
     const int spr = srcpos[r], spc = srcpos[c];
@@ -123,7 +124,9 @@ struct Front {
     if (sr == (spc >> 24) && sr < 2) {
       const double2* U = sr ? U1 : U0;
       const int ld = sr ? ld1 : ld0;
-      return U[(size_t)(spc & 0xffffff) * ld + (spr & 0xffffff)];
+      int pr = spr & 0xffffff, pc = spc & 0xffffff;
+      if (sym && pr < pc) { const int t = pr; pr = pc; pc = t; }
+      return U[(size_t)pc * ld + pr];
     }
     const int gr = node[r], gc = node[c];
     return o.a(gr & 0xffff, gr >> 16, gc & 0xffff, gc >> 16);
@@ -134,7 +137,9 @@ struct Front {
     if (sr == (spc >> 24) && sr < 2) {
       const int ld = sr ? ld1 : ld0;
       const double2* R = (sr ? U1 : U0) + (size_t)ld * ld;
-      return R[(size_t)(spc & 0xffffff) * ld + (spr & 0xffffff)];
+      const int pr = spr & 0xffffff, pc = spc & 0xffffff;
+      if (sym && pr < pc) { const double2 v = R[(size_t)pr * ld + pc]; return make_double2(-v.x, v.y); }
+      return R[(size_t)pc * ld + pr];
     }
     const int gr = node[r], gc = node[c];
     return o.s(gr & 0xffff, gr >> 16, gc & 0xffff, gc >> 16);
@@ -175,7 +180,7 @@ template <> struct MfmaT<true> {
 };
 
 template <int NT, bool F32, int TM, int TN, bool C3, class LA, class LB, class LC, class SC>
-__device__ __forceinline__ void gemm_tiles(int M, int N, int K, LA loadA, LB loadB, LC loadC, SC storeC) {
+__device__ __forceinline__ void gemm_tiles(int M, int N, int K, int tri, LA loadA, LB loadB, LC loadC, SC storeC) {
   typedef MfmaT<F32> T;
   typedef typename T::e E;
   constexpr int PD = 1;
@@ -184,8 +189,13 @@ __device__ __forceinline__ void gemm_tiles(int M, int N, int K, LA loadA, LB loa
   const int tm = (M + 16 * TM - 1) / (16 * TM), tn = (N + 16 * TN - 1) / (16 * TN);
   const int lr = lane & 15, lk = lane >> 4;
   const int nk = (K + 3) >> 2;
-  for (int t = wave; t < tm * tn; t += NT / 64) {
+  int mine = -1;   // tiles are dealt to the waves in turn, skipped ones excluded
+  for (int t = 0; t < tm * tn; ++t) {
     const int r0 = (t % tm) * 16 * TM, c0 = (t / tm) * 16 * TN;
+    // tri > 0: tiles wholly inside columns < tri and strictly above the
+    // diagonal are not formed (the caller mirrors them)
+    if (c0 + 16 * TN <= tri && c0 >= r0 + 16 * TM) continue;
+    if (++mine % (NT / 64) != wave) continue;
     // 4M: acc[0] = Re, acc[1] = Im.  3M: acc[0] = sum aR bR, acc[1] = sum aI bI,
     // acc[2] = sum (aR + aI)(bR + bI); Re = acc0 - acc1, Im = acc2 - acc0 - acc1.
     typename T::acc acc[NACC][TM][TN];
@@ -278,8 +288,8 @@ __device__ __forceinline__ void gemm_tiles(int M, int N, int K, LA loadA, LB loa
 
 template <int NT, class LA, class LB, class LC, class SC>
 __device__ __forceinline__ void gemm_sub(int M, int N, int K, LA loadA, LB loadB, LC loadC, SC storeC) {
-  if (N <= 16) gemm_tiles<NT, false, 2, 1, false>(M, N, K, loadA, loadB, loadC, storeC);
-  else gemm_tiles<NT, false, 2, 2, false>(M, N, K, loadA, loadB, loadC, storeC);
+  if (N <= 16) gemm_tiles<NT, false, 2, 1, false>(M, N, K, 0, loadA, loadB, loadC, storeC);
+  else gemm_tiles<NT, false, 2, 2, false>(M, N, K, 0, loadA, loadB, loadC, storeC);
 }
 
 // The Schur-complement products of an elimination, with the wave tile picked
@@ -288,11 +298,11 @@ __device__ __forceinline__ void gemm_sub(int M, int N, int K, LA loadA, LB loadB
 // only decides which wave computes which output block: every entry sees the
 // same k-order, so the result does not depend on TC.
 template <int NT, bool F32, int TC, bool C3, class LA, class LB, class LC, class SC>
-__device__ __forceinline__ void gemm_schur(int M, int N, int K, LA loadA, LB loadB, LC loadC, SC storeC) {
+__device__ __forceinline__ void gemm_schur(int M, int N, int K, int tri, LA loadA, LB loadB, LC loadC, SC storeC) {
   constexpr int TM = (TC == 0 || TC == 1) ? 2 : 1;
   constexpr int TN = (TC == 0 || TC == 2) ? 2 : 1;
-  if (TN == 2 && N <= 16) gemm_tiles<NT, F32, TM, 1, C3>(M, N, K, loadA, loadB, loadC, storeC);
-  else gemm_tiles<NT, F32, TM, TN, C3>(M, N, K, loadA, loadB, loadC, storeC);
+  if (TN == 2 && N <= 16) gemm_tiles<NT, F32, TM, 1, C3>(M, N, K, tri, loadA, loadB, loadC, storeC);
+  else gemm_tiles<NT, F32, TM, TN, C3>(M, N, K, tri, loadA, loadB, loadC, storeC);
 }
 
 // Inverse of the w x w unit-lower triangle held below the diagonal of L.tri
@@ -580,7 +590,7 @@ __global__ __launch_bounds__(NT, 3) void k_stage(StageArgs a) {
     __syncthreads();
     const Front fr{L.node, L.srcpos, pool + E.src0, pool + E.src1, E.ld0, E.ld1,
                    Orig{a.H, a.sigma + (size_t)e * 2 * a.Nx * a.Nx, a.sless + (size_t)e * 2 * a.Nx * a.Nx,
-                        a.energies[e], a.Nx, a.Ny, a.nst}};
+                        a.energies[e], a.Nx, a.Ny, a.nst}, a.sym};
     // 1. assemble the tall block [A_g(S,S); A_g(B,S)]; the other blocks of A_g
     //    and all of Sigma_g are gathered from their sources by the products
     for_each_rc<NT>(n, s, [&](int r, int c) { FA[(size_t)c * n + r] = fr.a(r, c); });
@@ -604,16 +614,21 @@ __global__ __launch_bounds__(NT, 3) void k_stage(StageArgs a) {
     auto b2 = [=](int k, int c) { return conjd(FA[(size_t)k * n + s + c]); };
     auto c2 = [=](int r, int c) { return W[(size_t)(s + c) * b + r]; };
     auto s2 = [=](int r, int c, double2 v) { Ro[(size_t)c * b + r] = v; };
+    // with a.sym, U is complex symmetric and R anti-Hermitian: their tiles
+    // above the diagonal are not formed, and every reader of U and R takes
+    // an upper entry from its mirror below the diagonal
+    const int tri = a.sym ? b : 0;
     if (E.f32) {
-      gemm_schur<NT, true, TC, CM == 1>(b, b + n, s, l_, b1, c1, s1);
+      gemm_schur<NT, true, TC, CM == 1>(b, b + n, s, tri, l_, b1, c1, s1);
       __syncthreads();
-      gemm_schur<NT, true, TC, CM == 1>(b, b, s, a2, b2, c2, s2);
+      gemm_schur<NT, true, TC, CM == 1>(b, b, s, tri, a2, b2, c2, s2);
     } else {
-      gemm_schur<NT, false, TC, CM == 1>(b, b + n, s, l_, b1, c1, s1);
+      gemm_schur<NT, false, TC, CM == 1>(b, b + n, s, tri, l_, b1, c1, s1);
       __syncthreads();
-      gemm_schur<NT, false, TC, CM == 1>(b, b, s, a2, b2, c2, s2);
+      gemm_schur<NT, false, TC, CM == 1>(b, b, s, tri, a2, b2, c2, s2);
     }
     __syncthreads();
+
   }
 }
 
@@ -644,7 +659,8 @@ __global__ __launch_bounds__(NT, 3) void k_final(StageArgs a, OutArgs o) {
     double2* G = pool + E.dst;                    // G(K,K), bp x bp
     for (int k = tid; k < bp; k += NT) L.perm[k] = k;
     for_each_rc<NT>(n, bp, [&](int r, int c) {
-      FA[(size_t)c * n + r] = r < bp ? Uin[(size_t)c * bp + r] : make_double2(r - bp == c ? 1.0 : 0.0, 0.0);
+      FA[(size_t)c * n + r] = r < bp ? Uin[a.sym && r < c ? (size_t)r * bp + c : (size_t)c * bp + r]
+                                     : make_double2(r - bp == c ? 1.0 : 0.0, 0.0);
     });
     __syncthreads();
     if (tall_lu<RPT, NB>(L, FA, n, bp) && tid == 0) a.status[e] = 1;
@@ -653,8 +669,12 @@ __global__ __launch_bounds__(NT, 3) void k_final(StageArgs a, OutArgs o) {
     for_each_rc<NT>(bp, bp, [&](int i, int k) { G[(size_t)L.perm[k] * bp + i] = FA[(size_t)k * n + bp + i]; });
     __syncthreads();
     // T = R_K G^dagger   (gemm_sub returns 0 - R G^dagger)
+    const int sym = a.sym;
     gemm_sub<NT>(bp, bp, bp,
-             [=](int r, int k) { return Rin[(size_t)k * bp + r]; },
+             [=](int r, int k) {
+               if (sym && r < k) { const double2 v = Rin[(size_t)r * bp + k]; return make_double2(-v.x, v.y); }
+               return Rin[(size_t)k * bp + r];
+             },
              [=](int k, int c) { return conjd(G[(size_t)k * bp + c]); },
              [=](int r, int c) { return zero2(); },
              [=](int r, int c, double2 v) { T[(size_t)c * bp + r] = make_double2(-v.x, -v.y); });

@@ -35,6 +35,7 @@ struct StageArgs {
   long long ws_stride;
   int Nx, Ny, nst;
   int* status;            // per energy of this pass: 1 = zero pivot met
+  int sym;                // 1: A complex symmetric and Sigma< anti-Hermitian (form half of U and R)
 };
 
 struct OutArgs {

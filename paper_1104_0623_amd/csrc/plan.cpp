@@ -41,10 +41,12 @@ int count_bonds(int Nx, int Ny, int stencil) {
   return n;
 }
 
-double elim_flops(const Elim& e) {
+double elim_flops(const Elim& e, bool symmetric) {
   double s = e.s, b = e.b;
   if (e.kind == K_FINAL) return 8.0 * 2.0 * s * s * s;
-  return 8.0 * (s * s * s / 3.0 + 2.0 * s * s * b + 3.0 * s * b * b);
+  // with U complex symmetric and R anti-Hermitian only half of U = A(B,B) - L A(S,B)
+  // and of R = W(:,B) - W(:,S) L^dagger is formed: s b^2 fewer multiply-adds
+  return 8.0 * (s * s * s / 3.0 + 2.0 * s * s * b + (symmetric ? 2.0 : 3.0) * s * b * b);
 }
 
 namespace {
@@ -340,9 +342,11 @@ struct Builder {
       for (int k = st.first; k < st.first + st.count; ++k) {
         const Elim& e = P.elims[k];
         P.max_n = std::max(P.max_n, e.n); P.max_s = std::max(P.max_s, e.s); P.max_b = std::max(P.max_b, e.b);
-        double f = elim_flops(e);
-        if (st.variant < 0) { P.flops[0] += f; P.flops[1] += f; }
-        else P.flops[st.variant] += f;
+        for (int sym = 0; sym < 2; ++sym) {
+          const double f = elim_flops(e, sym != 0);
+          if (st.variant < 0) { P.flops[sym][0] += f; P.flops[sym][1] += f; }
+          else P.flops[sym][st.variant] += f;
+        }
       }
     return "";
   }

@@ -184,6 +184,34 @@ def test_3m_complex_products_against_dense(Nx, Ny, stencil, leaf):
     compare(out, ref, prob, label=f"3M {Nx}x{Ny}/{stencil}/leaf{leaf}")
 
 
+@pytest.mark.parametrize("Nx,Ny,stencil,leaf", [(16, 16, 5, 4), (33, 20, 9, 8), (1, 11, 5, 2), (24, 40, 5, 8),
+                                                (12, 9, 9, 4)])
+def test_symmetric_form_against_dense(Nx, Ny, stencil, leaf):
+    """Half of every U and R formed, the rest mirrored (A complex symmetric,
+    Sigma< anti-Hermitian for these inputs)."""
+    f = find()
+    E = np.array([0.41 + 1e-6j, -2.9 + 1e-6j, 1.3 + 1e-3j])
+    prob = inputs.make_problem(Nx, Ny, stencil, vmax=1.0, seed=Nx * 5 + Ny, energies=E, fL=1.0, fR=0.3)
+    ref = dense.dense_solve(Nx, Ny, stencil, prob["H"], E, prob["sigma"], prob["sigma_less"])
+    for mixed in (False, True):
+        plan = f.Plan(Nx, Ny, stencil, leaf=leaf, symmetric=True,
+                      precision=f.PREC_MIXED if mixed else f.PREC_FP64)
+        out = f.run_problem(plan, prob, want_bonds=True)
+        compare(out, ref, prob, tol=MIXED_SMALL_TOL if mixed else TOL, label=f"sym {Nx}x{Ny} mixed={mixed}")
+
+
+def test_symmetric_form_c2_against_rgf_and_flops():
+    f = find()
+    prob = inputs.make_preset("c2_64x64")
+    ref = rgf.rgf_solve(64, 64, 5, prob["H"], prob["energies"], prob["sigma"], prob["sigma_less"])
+    plan = f.Plan(64, 64, 5, symmetric=True)
+    out = f.run_problem(plan, prob, want_bonds=True)
+    compare(out, ref, prob, label="sym c2")
+    # the flop model drops s b^2 complex multiply-adds per elimination
+    general = f.Plan(64, 64, 5).flops_per_energy()
+    assert 0.6 * general < plan.flops_per_energy() < general
+
+
 def test_3m_c2_64x64_against_rgf():
     f = find()
     prob = inputs.make_preset("c2_64x64")

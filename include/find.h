@@ -217,6 +217,7 @@ enum {
   FIND_EF_DST,         /* pool offset of U (b x b); R follows at DST + b*b     */
   FIND_EF_MAP,         /* first entry of this elimination's map (n entries)    */
   FIND_EF_CLUSTER, FIND_EF_PHASE, FIND_EF_LEVEL,
+  FIND_EF_RZERO,       /* 1: Sigma< vanishes on the front, so R = 0 (not formed) */
   FIND_EF_FIELDS
 };
 /* Phases: 0 upward, 1 downward, 2 leaf extraction, 3 final leaf block.

@@ -618,7 +618,12 @@ __global__ __launch_bounds__(NT, 3) void k_stage(StageArgs a) {
     // above the diagonal are not formed, and every reader of U and R takes
     // an upper entry from its mirror below the diagonal
     const int tri = a.sym ? b : 0;
-    if (E.f32) {
+    if (E.rzero) {
+      // Sigma< vanishes on this front: R = 0, and only U = A(B,B) - L A(perm,B) is formed
+      for_each_rc<NT>(b, b, [&](int r, int c) { Ro[(size_t)c * b + r] = zero2(); });
+      if (E.f32) gemm_schur<NT, true, TC, CM == 1>(b, b, s, tri, l_, b1, c1, s1);
+      else gemm_schur<NT, false, TC, CM == 1>(b, b, s, tri, l_, b1, c1, s1);
+    } else if (E.f32) {
       gemm_schur<NT, true, TC, CM == 1>(b, b + n, s, tri, l_, b1, c1, s1);
       __syncthreads();
       gemm_schur<NT, true, TC, CM == 1>(b, b, s, tri, a2, b2, c2, s2);

@@ -14,7 +14,7 @@ struct ElimDev {
   int map;                // first map entry
   int aux;                // final leaf block: index of its output record
   int f32;                // 1: Schur/Sigma products in FP32 (mixed form)
-  int pad;
+  int rzero;              // 1: Sigma< vanishes on the front: R = 0, only U is formed
 };
 
 struct LeafOutDev { int elim_dst_lo, elim_dst_hi, bprime, n_nodes, node_first, bond_first, n_bonds, pad; };

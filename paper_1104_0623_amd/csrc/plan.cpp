@@ -45,7 +45,10 @@ double elim_flops(const Elim& e, bool symmetric) {
   double s = e.s, b = e.b;
   if (e.kind == K_FINAL) return 8.0 * 2.0 * s * s * s;
   // with U complex symmetric and R anti-Hermitian only half of U = A(B,B) - L A(S,B)
-  // and of R = W(:,B) - W(:,S) L^dagger is formed: s b^2 fewer multiply-adds
+  // and of R = W(:,B) - W(:,S) L^dagger is formed: s b^2 fewer multiply-adds.
+  // With R = 0 (no Sigma< in the front) W and R are not formed: LU s^3/3 + s^2 b / 2,
+  // L s^2 b / 2, U s b^2 (half of it when symmetric)
+  if (e.rzero) return 8.0 * (s * s * s / 3.0 + s * s * b + (symmetric ? 0.5 : 1.0) * s * b * b);
   return 8.0 * (s * s * s / 3.0 + 2.0 * s * s * b + (symmetric ? 2.0 : 3.0) * s * b * b);
 }
 
@@ -221,6 +224,10 @@ struct Builder {
         Cluster& c = P.cl[q];
         if (c.height != h) continue;
         Elim e; e.phase = PH_UP; e.cluster = q; e.level = c.depth; e.dst = c.up_off;
+        // Sigma< is supported on the contact columns y = 0 and y = Ny - 1 only;
+        // a cluster away from both has Sigma<(C, C) = 0, and so R = 0 for it and
+        // (recursively) for all its descendants
+        e.rzero = (c.r.y0 > 0 && c.r.y0 + c.r.h < Ny) ? 1 : 0;
         std::vector<int> list, src, pos;
         if (c.leaf()) {
           list = cluster_nodes(c.r);

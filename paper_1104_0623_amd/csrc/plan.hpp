@@ -32,6 +32,9 @@ struct Elim {
   int64_t dst = -1;
   int map = 0;
   int cluster = -1, phase = 0, level = 0;
+  // 1: Sigma< vanishes on every node of the front (an upward-pass cluster that
+  // touches neither contact column), so R = 0 and only U is formed
+  int rzero = 0;
 };
 
 struct Stage { int first, count, phase, variant; };

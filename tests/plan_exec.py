@@ -31,7 +31,7 @@ def orig_entries(nodes_r, nodes_c, Nx, Ny, Hm, E, sig, sless):
     return A, S
 
 
-def execute(plan_export: dict, Nx, Ny, stencil, Hm, E, sig, sless, want_bonds=True):
+def execute(plan_export: dict, Nx, Ny, stencil, Hm, E, sig, sless, want_bonds=True, record=None):
     ex = plan_export
     elims, maps, stages = ex["elims"], ex["maps"], ex["stages"]
     variant = 1 if want_bonds else 0
@@ -63,6 +63,8 @@ def execute(plan_export: dict, Nx, Ny, stencil, Hm, E, sig, sless, want_bonds=Tr
             else:
                 U, R = A[Bx, Bx].copy(), S[Bx, Bx].copy()
             pool[dst] = (U, R)
+            if record is not None:
+                record[k] = (U, R)
     nn = Nx * Ny
     dG = np.zeros(nn, np.complex128); dL = np.zeros(nn, np.complex128)
     nb = int(ex["outbonds"][:, 0].max()) + 1 if ex["outbonds"].size else 0

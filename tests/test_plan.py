@@ -87,6 +87,49 @@ def test_tile_and_complex_mode_options():
     assert L.find_plan_set_tiles(plan.handle, None, n) == find.FIND_E_ARG
 
 
+@pytest.mark.parametrize("Nx,Ny,stencil,leaf", [(12, 20, 5, 3), (9, 16, 9, 4)])
+def test_zero_sigma_fronts_are_flagged_exactly(Nx, Ny, stencil, leaf):
+    """Upward eliminations flagged R = 0 (the cluster touches neither contact
+    column) have an exactly zero R in the definition-level executor, and the
+    flop model drops their W and R products."""
+    from tests.plan_exec import execute
+    find = findlib()
+    E = np.array([0.37 + 1e-3j])
+    prob = inputs.make_problem(Nx, Ny, stencil, vmax=1.0, seed=4, energies=E, fL=1.0, fR=0.5)
+    p = find.Plan(Nx, Ny, stencil, leaf=leaf)
+    ex = p.export()
+    rec = {}
+    Hm = dense.hamiltonian_matrix(Nx, Ny, prob["H"])
+    execute(ex, Nx, Ny, stencil, Hm, E[0], prob["sigma"][0], prob["sigma_less"][0], want_bonds=False,
+            record=rec)
+    el = ex["elims"]
+    flagged = [k for k in range(len(el)) if el[k][13] == 1]
+    assert flagged, "no front away from the contacts"
+    for k in range(len(el)):
+        if k not in rec:
+            continue
+        U, R = rec[k]
+        if el[k][13] == 1:
+            assert el[k][11] == 0                     # upward pass only
+            assert np.all(R == 0), k
+        elif el[k][11] == 0 and el[k][0] == 0 and R.size:
+            assert np.any(R != 0), k                  # flag is as tight as the structure allows
+    # flop model: a flagged elimination counts s^3/3 + s^2 b + s b^2 multiply-adds
+    ok = 0.0
+    for first, count, phase, var in ex["stages"]:
+        if var == 1:
+            continue
+        for k in range(first, first + count):
+            kind, s_, b_ = el[k][0], float(el[k][1]), float(el[k][2])
+            if kind == 1:
+                ok += 16 * s_ ** 3
+            elif el[k][13]:
+                ok += 8 * (s_ ** 3 / 3 + s_ ** 2 * b_ + s_ * b_ ** 2)
+            else:
+                ok += 8 * (s_ ** 3 / 3 + 2 * s_ ** 2 * b_ + 3 * s_ * b_ ** 2)
+    assert abs(p.flops_per_energy(False) - ok) <= 1e-9 * ok
+
+
 def test_tree_shape_128():
     find = findlib()
     p = find.Plan(128, 128, 5)

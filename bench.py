@@ -119,6 +119,7 @@ def main() -> int:
     ap.add_argument("--general", action="store_true",
                     help="do not assert that A is complex symmetric and Sigma< anti-Hermitian (true for these "
                          "inputs, so by default only half of each U and R is formed)")
+    ap.add_argument("--streams", type=int, default=2, help="energy groups solved concurrently (0/1 = one)")
     ap.add_argument("--autotune", action="store_true",
                     help="run the autotuner even if the tuning table has an entry for this workload")
     ap.add_argument("--tiles", default="",
@@ -162,7 +163,8 @@ def main() -> int:
     dL = torch.empty_like(dG)
     prec = find.PREC_MIXED if args.precision == "mixed" else find.PREC_FP64
     cmode = find.CPLX_3M if args.complex_mode == "3m" else find.CPLX_4M
-    plan = find.Plan(Nx, Ny, st, leaf=args.leaf, precision=prec, complex_mode=cmode, symmetric=not args.general)
+    plan = find.Plan(Nx, Ny, st, leaf=args.leaf, precision=prec, complex_mode=cmode, symmetric=not args.general,
+                     streams=args.streams)
     stream = torch.cuda.Stream()          # non-default stream (graph capture needs one)
     torch.cuda.set_stream(stream)
     tune_s = 0.0
@@ -242,7 +244,7 @@ def main() -> int:
         "config": {"workload": f"FIND diag G + diag G<, {Nx}x{Ny} mesh, {st}-point stencil, {nE} energies "
                                f"per step ({args.preset}), {args.precision}",
                    "Nx": Nx, "Ny": Ny, "stencil": st, "energies_per_step": nE, "precision": args.precision,
-                   "leaf": args.leaf, "complex_mode": args.complex_mode, "symmetric": not args.general,
+                   "leaf": args.leaf, "complex_mode": args.complex_mode, "symmetric": not args.general, "streams": args.streams,
                    "launch": "eager" if args.no_graph else "hipGraph replay per batch",
                    "stage_tiles": "".join(str(t) for t in tiles),
                    "stage_tiles_from": tiles_from,

@@ -96,7 +96,13 @@ typedef enum { FIND_CPLX_4M = 0, FIND_CPLX_3M = 1 } find_complex_mode;
  *                 triangles are formed and the upper triangles are mirrored
  *                 (s b^2 fewer complex multiply-adds per elimination; the
  *                 flop model of find_plan_flops follows).  Inputs that break
- *                 the assertion give wrong results.  0 (default) = general. */
+ *                 the assertion give wrong results.  0 (default) = general.
+ *   streams       energy groups solved concurrently inside one pass (0 or 1
+ *                 = one, on the caller's stream; 2..4 = that many groups, each
+ *                 on a stream of the plan, forked from and joined back to the
+ *                 caller's stream with events, each with its own workspace),
+ *                 so that one group's small late stages overlap another's.
+ *                 Results do not depend on it. */
 typedef struct {
   int leaf;
   int precision;
@@ -105,7 +111,8 @@ typedef struct {
   size_t workspace_budget;
   int complex_mode;
   int symmetric;
-  int reserved[6];
+  int streams;
+  int reserved[5];
 } find_plan_opts;
 
 /* Build the cluster tree, boundary sets, gather maps and level schedule for

@@ -66,6 +66,10 @@ struct DevState {
   std::vector<hipEvent_t> ev;
   std::vector<double> ev_flops;
   size_t ev_used = 0;
+  // concurrent energy groups: one stream and join event per group, one fork event
+  std::vector<hipStream_t> lane_st;
+  std::vector<hipEvent_t> lane_ev;
+  hipEvent_t fork_ev = nullptr;
 };
 
 __global__ void k_fill_int(int* p, int n, int v) {
@@ -94,6 +98,9 @@ void free_dev(DevState& d) {
   if (hipGetDevice(&cur) != hipSuccess) cur = -1;
   if (d.device >= 0) (void)hipSetDevice(d.device);
   for (hipEvent_t e : d.ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : d.lane_ev) (void)hipEventDestroy(e);
+  if (d.fork_ev) (void)hipEventDestroy(d.fork_ev);
+  for (hipStream_t s : d.lane_st) (void)hipStreamDestroy(s);
   void* ptrs[] = {d.d_elims, d.d_map_node, d.d_map_srcpos, d.d_leafout[0], d.d_leafout[1],
                   d.d_outnode, d.d_outbond, d.pool, d.ws, d.status};
   for (void* p : ptrs)
@@ -216,6 +223,12 @@ size_t ws_for(const DevState& d, int ec) {
   return w;
 }
 
+// Energy groups run concurrently (each on its own stream with its own
+// workspace) inside one pass.
+int lanes_of(const find_plan_s* p) { return std::max(1, std::min(4, p->opts.streams)); }
+size_t lane_ws(const DevState& d, int ec, int lanes) { return ws_for(d, (ec + lanes - 1) / lanes); }
+size_t ws_total(const DevState& d, int ec, int lanes) { return size_t(lanes) * lane_ws(d, ec, lanes); }
+
 size_t budget_of(const find_plan_s* p) {
   return p->opts.workspace_budget ? p->opts.workspace_budget : (size_t(64) << 30);
 }
@@ -226,7 +239,8 @@ int chunk_energies(const find_plan_s* p, const DevState& d, int nE) {
   const size_t budget = budget_of(p);
   int ec = nE;
   if (p->opts.max_energies > 0) ec = std::min(ec, p->opts.max_energies);
-  auto need = [&](int c) { return ws_for(d, c) * sizeof(double2) + d.maps_bytes + per_e * size_t(c); };
+  const int lanes = lanes_of(p);
+  auto need = [&](int c) { return ws_total(d, c, lanes) * sizeof(double2) + d.maps_bytes + per_e * size_t(c); };
   while (ec > 1 && need(ec) > budget) ec = std::max(1, std::min(ec - 1, int(ec * double(budget) / double(need(ec)))));
   return need(ec) <= budget ? ec : 0;
 }
@@ -258,6 +272,7 @@ find_status find_plan_create(int Nx, int Ny, int stencil, const find_plan_opts* 
   if (o.complex_mode != FIND_CPLX_4M && o.complex_mode != FIND_CPLX_3M)
     return fail(FIND_E_ARG, "find_plan_create: unknown complex_mode");
   if (o.symmetric != 0 && o.symmetric != 1) return fail(FIND_E_ARG, "find_plan_create: symmetric must be 0 or 1");
+  if (o.streams < 0 || o.streams > 4) return fail(FIND_E_ARG, "find_plan_create: streams must be 0..4");
   if ((long long)Nx * Ny > (1LL << 24)) return fail(FIND_E_UNSUPPORTED, "find_plan_create: mesh larger than 2^24 nodes");
   find_plan_s* p = new (std::nothrow) find_plan_s();
   if (!p) return fail(FIND_E_NOMEM, "find_plan_create: host allocation failed");
@@ -369,7 +384,7 @@ find_status find_plan_footprint(find_plan plan, int nE, int want_bonds, size_t* 
                   P.outnode_node.size() * 2) * 4;
   int ec = chunk_energies(plan, d, nE);
   if (ec < 1) ec = 1;
-  *bytes = ws_for(d, ec) * sizeof(double2) + d.maps_bytes +
+  *bytes = ws_total(d, ec, lanes_of(plan)) * sizeof(double2) + d.maps_bytes +
            (size_t(P.pool_per_energy) * sizeof(double2) + sizeof(int)) * size_t(ec);
   return FIND_OK;
 }
@@ -386,7 +401,7 @@ find_status prepare(find_plan_s* plan, int nE, hipStream_t st, DevState** dout, 
   if (fs != FIND_OK) return fs;
   *ec = chunk_energies(plan, *d, nE);
   if (*ec < 1) return fail(FIND_E_NOMEM, "find_solve: workspace budget too small for one energy");
-  const size_t ws_need = ws_for(*d, *ec);
+  const size_t ws_need = ws_total(*d, *ec, lanes_of(plan));
   if (d->ws_elems < ws_need) {
     if (d->ws) { HIPCHK(hipStreamSynchronize(st)); HIPCHK(hipFree(d->ws)); d->ws = nullptr; d->ws_elems = 0; }
     if (hipMalloc(&d->ws, ws_need * sizeof(double2)) != hipSuccess)
@@ -406,6 +421,16 @@ find_status prepare(find_plan_s* plan, int nE, hipStream_t st, DevState** dout, 
       return fail(FIND_E_NOMEM, "find_solve: status allocation failed");
     d->status_len = nE;
   }
+  const int lanes = lanes_of(plan);
+  while (int(d->lane_st.size()) < lanes && lanes > 1) {
+    hipStream_t s2;
+    hipEvent_t e2;
+    HIPCHK(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));   // default priority
+    d->lane_st.push_back(s2);
+    HIPCHK(hipEventCreateWithFlags(&e2, hipEventDisableTiming));
+    d->lane_ev.push_back(e2);
+  }
+  if (lanes > 1 && !d->fork_ev) HIPCHK(hipEventCreateWithFlags(&d->fork_ev, hipEventDisableTiming));
   *dout = d;
   return FIND_OK;
 }
@@ -426,7 +451,7 @@ void pass_args(const find_plan_s* plan, const DevState* d, int variant, int e0, 
   a.sigma = reinterpret_cast<const double2*>(sigma) + size_t(e0) * 2 * nx2;
   a.sless = reinterpret_cast<const double2*>(sigma_less) + size_t(e0) * 2 * nx2;
   a.pool = d->pool; a.pool_stride = P.pool_per_energy;
-  a.ws = d->ws;
+  a.ws = d->ws;   // (an energy group of a multi-stream pass offsets this)
   a.Nx = P.Nx; a.Ny = P.Ny; a.nst = P.stencil == 9 ? 5 : 3;
   a.status = d->status + e0;
   a.sym = plan->opts.symmetric;
@@ -477,32 +502,71 @@ find_status find_solve(find_plan plan, int nE, const double* energies, const dou
   if (plan->profiling) d->ev_used = 0;  // the profile describes this solve
   hipLaunchKernelGGL(k_fill_int, dim3((nE + 255) / 256), dim3(256), 0, st, d->status, nE, 0);
   HIPCHK(hipGetLastError());
+  const int lanes = lanes_of(plan);
+  const size_t lws = lane_ws(*d, ec, lanes);
   for (int e0 = 0; e0 < nE; e0 += ec) {
     const int ne = std::min(ec, nE - e0);
-    StageArgs a;
-    OutArgs o;
-    pass_args(plan, d, variant, e0, ne, energies, H, sigma, sigma_less, diag_G, diag_Gless, bond_G, bond_Gless,
-              bond_J, &a, &o);
-    for (size_t k = 0; k < d->stages.size(); ++k) {
-      const DevStage& s2 = d->stages[k];
-      if (s2.variant >= 0 && s2.variant != variant) continue;
-      if ((long long)s2.count * ne < 1) continue;
-      if (plan->profiling) {
+    // energy groups of this pass: one on the caller's stream, or `lanes`
+    // groups on the plan's streams, forked from and joined back to it
+    const int ng = (lanes > 1 && ne > 1) ? std::min(lanes, ne) : 1;
+    const int per = (ne + ng - 1) / ng;
+    if (ng > 1) {
+      if (plan->profiling) {   // one event pair around the whole pass
         while (d->ev.size() < 2 * (d->ev_used + 1)) {
           hipEvent_t ev;
           HIPCHK(hipEventCreate(&ev));
           d->ev.push_back(ev);
         }
         if (d->ev_flops.size() < d->ev_used + 1) d->ev_flops.resize(d->ev_used + 1);
-        d->ev_flops[d->ev_used] = s2.flops_per_energy * ne;
+        double f = 0.0;
+        for (const DevStage& s2 : d->stages)
+          if (s2.variant < 0 || s2.variant == variant) f += s2.flops_per_energy * ne;
+        d->ev_flops[d->ev_used] = f;
         HIPCHK(hipEventRecord(d->ev[2 * d->ev_used], st));
       }
-      const hipError_t he = launch_stage_k(plan, d, int(k), a, o, plan->tiles[k], st);
-      if (he != hipSuccess) return fail(FIND_E_DEVICE, std::string("stage launch: ") + hipGetErrorString(he));
-      if (plan->profiling) {
-        HIPCHK(hipEventRecord(d->ev[2 * d->ev_used + 1], st));
-        ++d->ev_used;
+      HIPCHK(hipEventRecord(d->fork_ev, st));
+    }
+    for (int g = 0; g < ng; ++g) {
+      const int g0 = e0 + g * per, gn = std::min(per, e0 + ne - g0);
+      if (gn < 1) continue;
+      hipStream_t sg = ng > 1 ? d->lane_st[g] : st;
+      if (ng > 1) HIPCHK(hipStreamWaitEvent(sg, d->fork_ev, 0));
+      StageArgs a;
+      OutArgs o;
+      pass_args(plan, d, variant, g0, gn, energies, H, sigma, sigma_less, diag_G, diag_Gless, bond_G, bond_Gless,
+                bond_J, &a, &o);
+      a.ws = d->ws + size_t(g) * lws;
+      a.pool = d->pool + size_t(g0 - e0) * size_t(plan->P.pool_per_energy);   // kernels index energies from 0
+      for (size_t k = 0; k < d->stages.size(); ++k) {
+        const DevStage& s2 = d->stages[k];
+        if (s2.variant >= 0 && s2.variant != variant) continue;
+        if ((long long)s2.count * gn < 1) continue;
+        const bool prof = plan->profiling && ng == 1;
+        if (prof) {
+          while (d->ev.size() < 2 * (d->ev_used + 1)) {
+            hipEvent_t ev;
+            HIPCHK(hipEventCreate(&ev));
+            d->ev.push_back(ev);
+          }
+          if (d->ev_flops.size() < d->ev_used + 1) d->ev_flops.resize(d->ev_used + 1);
+          d->ev_flops[d->ev_used] = s2.flops_per_energy * gn;
+          HIPCHK(hipEventRecord(d->ev[2 * d->ev_used], sg));
+        }
+        const hipError_t he = launch_stage_k(plan, d, int(k), a, o, plan->tiles[k], sg);
+        if (he != hipSuccess) return fail(FIND_E_DEVICE, std::string("stage launch: ") + hipGetErrorString(he));
+        if (prof) {
+          HIPCHK(hipEventRecord(d->ev[2 * d->ev_used + 1], sg));
+          ++d->ev_used;
+        }
       }
+      if (ng > 1) {
+        HIPCHK(hipEventRecord(d->lane_ev[g], sg));
+        HIPCHK(hipStreamWaitEvent(st, d->lane_ev[g], 0));
+      }
+    }
+    if (ng > 1 && plan->profiling) {
+      HIPCHK(hipEventRecord(d->ev[2 * d->ev_used + 1], st));
+      ++d->ev_used;
     }
   }
   plan->last_nE = nE;

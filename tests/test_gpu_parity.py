@@ -275,15 +275,30 @@ def test_mixed_precision_c2_and_c3_sampled():
     assert np.median(eg) <= 1e-3 and np.median(el) <= 1e-3, (np.median(eg), np.median(el))
 
 
-def test_hip_graph_capture_replays_match_eager():
+def test_concurrent_energy_groups_match_one_stream():
+    """Energy groups on the plan's own streams give the same bits as one stream
+    (also with several passes and the bond outputs)."""
+    f = find()
+    E = inputs.energies_linspace(-3.0, 3.0, 7)
+    prob = inputs.make_problem(20, 28, 9, vmax=1.0, seed=3, energies=E, fL=1.0, fR=0.0)
+    base = f.run_problem(f.Plan(20, 28, 9), prob, want_bonds=True)
+    for streams, max_e in ((2, 0), (3, 0), (4, 5), (2, 3)):
+        out = f.run_problem(f.Plan(20, 28, 9, streams=streams, max_energies=max_e), prob, want_bonds=True)
+        for k in base:
+            assert np.array_equal(out[k], base[k]), (streams, max_e, k)
+
+
+@pytest.mark.parametrize("streams", [0, 2])
+def test_hip_graph_capture_replays_match_eager(streams):
     """find_solve enqueues kernels only (no allocation after the first call,
-    no memset), so a caller can capture it in a hipGraph.  Every replay, with
-    unrelated eager work in between, equals the eager result bit for bit."""
+    no memset), so a caller can capture it in a hipGraph, also when it forks
+    energy groups onto the plan's streams.  Every replay, with unrelated eager
+    work in between, equals the eager result bit for bit."""
     import torch
     f = find()
     E = inputs.energies_linspace(-3.0, 3.0, 6)
     prob = inputs.make_problem(24, 33, 9, vmax=1.0, seed=9, energies=E, fL=1.0, fR=0.2)
-    plan = f.Plan(24, 33, 9)
+    plan = f.Plan(24, 33, 9, streams=streams)
     dev = torch.device("cuda")
     Et = torch.as_tensor(prob["energies"], device=dev); Ht = torch.as_tensor(prob["H"], device=dev)
     St = torch.as_tensor(prob["sigma"], device=dev); SLt = torch.as_tensor(prob["sigma_less"], device=dev)

@@ -26,17 +26,18 @@ PEAK = {"fp64": 78.6, "mixed": 157.3}   # MI355X dense MFMA TFLOP/s (FP64, FP32)
 # solve, from rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs (calibrated on a
 # plain copy; profiles/elim_kernels_c3_128x128_fp64.md).  Valid only for the
 # kernel source they were measured on.
-TRAFFIC_BYTES_PER_LAUNCH = 53506903066.6
-TRAFFIC_KERNEL_SHA = "72ab5654a4defe17"
-TRAFFIC_TILES = "44410000300000011000"
+TRAFFIC_BYTES_PER_LAUNCH = 24902128919.5
+TRAFFIC_KERNEL_SHA = "4ac1cf2dcaeb8955"
+TRAFFIC_TILES = "44511100300001151500"
+TRAFFIC_FORM = (True, 2)   # (symmetric, energy groups) of the counter runs
 
 
-def measured_traffic(preset: str, precision: str, tiles: str, cmode: str):
+def measured_traffic(preset: str, precision: str, tiles: str, cmode: str, form: tuple):
     import hashlib
     src = os.path.join(ROOT, "paper_1104_0623_amd", "csrc", "kernels.hip")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     if (sha != TRAFFIC_KERNEL_SHA or tiles != TRAFFIC_TILES or preset != "c3_128x128" or precision != "fp64"
-            or cmode != "4m"):
+            or cmode != "4m" or form != TRAFFIC_FORM):
         return None
     return TRAFFIC_BYTES_PER_LAUNCH
 
@@ -80,7 +81,7 @@ def serve_bench(args) -> dict:
         for rate in rates:
             trace = poisson_trace(args.serve_requests, rate=rate, seed=0)
             ex = GpuExecutor(n_slots=args.slots, precision=prec, plan_budget=16 << 30, cache_limit=96 << 30,
-                             keep_outputs=False)
+                             keep_outputs=False, symmetric=not args.general)
             # warm the plan cache (host trees, device maps) outside the timed trace
             for key in sorted({r.key for r in trace}):
                 plan = ex.cache.take(key)
@@ -252,7 +253,8 @@ def main() -> int:
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": measured_traffic(args.preset, args.precision, "".join(str(t) for t in tiles),
-                                                                 args.complex_mode),
+                                                                 args.complex_mode,
+                                                                 (not args.general, max(1, args.streams))),
                      "kernel": "k_stage + k_final (elimination kernels, all stage launches)",
                      "timing": "HIP events per stage launch" if args.no_graph else "HIP events around each graph replay",
                      "launches": nl, "kernel_ms_per_step": kms / args.steps,

@@ -71,8 +71,9 @@ class PlanCache:
     until the cached bytes would exceed the limit, then the least recently
     used are destroyed."""
 
-    def __init__(self, precision: int, plan_budget: int, limit_bytes: int):
+    def __init__(self, precision: int, plan_budget: int, limit_bytes: int, symmetric: bool = False):
         self.precision = precision
+        self.symmetric = symmetric
         self.plan_budget = plan_budget
         self.limit = limit_bytes
         self.idle = collections.OrderedDict()   # id(plan) -> (key, plan, bytes)
@@ -84,7 +85,8 @@ class PlanCache:
                 del self.idle[pid]
                 return plan
         self.created += 1
-        return find.Plan(*key, precision=self.precision, workspace_budget=self.plan_budget)
+        return find.Plan(*key, precision=self.precision, workspace_budget=self.plan_budget,
+                         symmetric=self.symmetric)
 
     def give(self, key, plan, nbytes: int, inflight_bytes: int):
         self.idle[id(plan)] = (key, plan, nbytes)
@@ -101,12 +103,13 @@ class GpuExecutor:
     """Runs requests through the HIP library, one stream per slot."""
 
     def __init__(self, n_slots: int, precision: int = find.PREC_FP64, plan_budget: int = 16 << 30,
-                 cache_limit: int = 96 << 30, device: str = "cuda", keep_outputs: bool = True):
+                 cache_limit: int = 96 << 30, device: str = "cuda", keep_outputs: bool = True,
+                 symmetric: bool = False):
         import torch
         self.torch = torch
         self.dev = torch.device(device)
         self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(n_slots)]
-        self.cache = PlanCache(precision, plan_budget, cache_limit)
+        self.cache = PlanCache(precision, plan_budget, cache_limit, symmetric)
         self.running = [None] * n_slots
         self.keep_outputs = keep_outputs
 

@@ -722,11 +722,12 @@ __global__ __launch_bounds__(NT, 3) void k_final(StageArgs a, OutArgs o) {
 }
 
 #ifndef FIND_TU
-#error "kernels.hip is compiled once per kernel family: -DFIND_TU=1, 2, 3 or 4"
+#error "kernels.hip is compiled once per kernel family: -DFIND_TU=1 .. 6"
 #endif
 // Launchers.  The source is compiled once per kernel family (FIND_TU = 1:
-// k_stage with 1 panel row per thread, 2: with 2, 3: with 4 and 8 and the
-// one-wave-per-front forms, 4: k_final) so that the families build in parallel.
+// k_stage with 1 panel row per thread, 2: with 2, 3: with 4 and 8, 4: k_final,
+// 5: the one-wave form of k_stage, 6: its two-wave form) so that the families
+// build in parallel.
 #define FIND_LAUNCH_STAGE(R, T, C)                                                            \
   if (tc == T && cm == C) {                                                                   \
     hipLaunchKernelGGL((k_stage<R, T, C, kThreads, kMaxFront>), dim3(grid), dim3(kThreads), 0, st, a); \
@@ -745,6 +746,8 @@ hipError_t launch_stage_r48(const StageArgs& a, int rpt, int tc, int cm, int gri
   if (rpt == 8) { FIND_LAUNCH_STAGE(8, 0, 0) FIND_LAUNCH_STAGE(8, 0, 1) }
   return hipErrorInvalidValue;
 }
+#endif
+#if FIND_TU == 5
 // one wave per front (fronts of at most kWaveMaxFront nodes)
 hipError_t launch_stage_w(const StageArgs& a, int rpt, int cm, int grid, hipStream_t st) {
 #define FIND_LAUNCH_W(R, C)                                                                    \
@@ -756,6 +759,8 @@ hipError_t launch_stage_w(const StageArgs& a, int rpt, int cm, int grid, hipStre
 #undef FIND_LAUNCH_W
   return hipErrorInvalidValue;
 }
+#endif
+#if FIND_TU == 6
 // two waves per front (fronts of at most kTwoWaveMaxFront nodes)
 hipError_t launch_stage_w2(const StageArgs& a, int rpt, int cm, int grid, hipStream_t st) {
 #define FIND_LAUNCH_W2(R, C)                                                                   \

@@ -184,10 +184,15 @@ find_status find_plan_profile(find_plan plan, double* kernel_ms, double* kernel_
  * (major-update) and eq. (gless-update-rule) (stages whose fronts exceed 512
  * nodes, and the final leaf blocks, have 0 only); 4 = one 64-thread workgroup
  * (a single wave) per front, for stages whose fronts have at most 128 nodes;
- * 5 = one 128-thread workgroup (two waves) per front, fronts of at most 256.
- * A configuration only decides which threads compute which part of the same
- * operations in the same order, so results are bitwise the same for every
- * configuration.
+ * 5 = one 128-thread workgroup (two waves) per front, fronts of at most 256;
+ * 6 = one 256-thread workgroup per front with 64x64 workgroup tiles whose
+ * operands the four waves share through LDS, for the Schur products and the
+ * LU trailing updates (stages whose fronts have at most 512 nodes, not the
+ * final leaf blocks).
+ * Configurations 0..3 and 6 only decide which threads compute which part of
+ * the same operations in the same order, so their results are bitwise the
+ * same; 4 and 5 factor fronts with narrower register panels (same
+ * operations, other rounding).
  *   find_plan_autotune runs one solve of the first min(nE, pass size)
  *   energies stage by stage, times every configuration of every stage `reps`
  *   times (reps < 1 means 2) with HIP events on `hip_stream`, keeps the
@@ -225,6 +230,8 @@ enum {
   FIND_EF_MAP,         /* first entry of this elimination's map (n entries)    */
   FIND_EF_CLUSTER, FIND_EF_PHASE, FIND_EF_LEVEL,
   FIND_EF_RZERO,       /* 1: Sigma< vanishes on the front, so R = 0 (not formed) */
+  FIND_EF_SSIG,        /* eliminated nodes carrying Sigma< (the first SSIG of S) */
+  FIND_EF_BSIG,        /* 1: some kept node carries Sigma<                       */
   FIND_EF_FIELDS
 };
 /* Phases: 0 upward, 1 downward, 2 leaf extraction, 3 final leaf block.

@@ -117,6 +117,12 @@ find_status upload(T** dptr, const std::vector<T>& h, size_t& bytes) {
   return FIND_OK;
 }
 
+// Workspace (complex elements) of one Schur elimination: the tall block
+// [A(S,S); A(B,S)] (n x s), L (b x s) and W_q (b x ssig).
+long long elim_ws(const Elim& e) {
+  return (long long)e.n * e.s + (long long)e.b * e.s + (long long)e.b * e.ssig;
+}
+
 find_status ensure_device(find_plan_s* p, DevState** out) {
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
@@ -144,7 +150,7 @@ find_status ensure_device(find_plan_s* p, DevState** out) {
       d.kind = e.kind; d.s = e.s; d.b = e.b; d.n = e.n;
       d.src0 = std::max<int64_t>(0, e.src_off[0]); d.src1 = std::max<int64_t>(0, e.src_off[1]);
       d.ld0 = e.src_ld[0]; d.ld1 = e.src_ld[1];
-      d.dst = e.dst; d.map = e.map; d.aux = -1; d.rzero = e.rzero;
+      d.dst = e.dst; d.map = e.map; d.aux = -1; d.rzero = e.rzero; d.ssig = e.ssig; d.bsig = e.bsig;
       // mixed form: FP32 products except the top-level eliminations, large
       // separators and the final leaf blocks, which stay FP64
       const int top = p->opts.fp64_top_levels == 0 ? 2 : p->opts.fp64_top_levels;
@@ -152,8 +158,8 @@ find_status ensure_device(find_plan_s* p, DevState** out) {
       maxn = std::max(maxn, e.n);
       ds_st.maxb = std::max(ds_st.maxb, e.b);
       ds_st.flops_per_energy += elim_flops(e, p->opts.symmetric != 0);
-      const long long need = e.kind == K_FINAL ? 3LL * e.b * e.b                     // [U; I] and T
-                                               : (long long)e.n * e.s + (long long)e.b * e.n;  // tall block and W
+      const long long need = e.kind == K_FINAL ? 3LL * e.b * e.b  // [U; I] and T
+                                               : elim_ws(e);          // tall block, L and W_q
       ds_st.ws_stride = std::max<long long>(ds_st.ws_stride, need);
     }
     if (maxn > kMaxFront) {
@@ -329,7 +335,7 @@ find_status find_plan_export(find_plan plan, int32_t* elims, int32_t* maps, int3
       r[FIND_EF_SRC1] = int32_t(e.src_off[1]); r[FIND_EF_LD1] = e.src_ld[1];
       r[FIND_EF_DST] = int32_t(e.dst); r[FIND_EF_MAP] = e.map;
       r[FIND_EF_CLUSTER] = e.cluster; r[FIND_EF_PHASE] = e.phase; r[FIND_EF_LEVEL] = e.level;
-      r[FIND_EF_RZERO] = e.rzero;
+      r[FIND_EF_RZERO] = e.rzero; r[FIND_EF_SSIG] = e.ssig; r[FIND_EF_BSIG] = e.bsig;
     }
   if (maps)
     for (size_t k = 0; k < P.map_node.size(); ++k) {
@@ -374,8 +380,7 @@ find_status find_plan_footprint(find_plan plan, int nE, int want_bonds, size_t* 
     DevStage ds{st.first, st.count, st.phase, st.variant, 0.0, 1, 0, 0, 1, nullptr};
     for (int k = st.first; k < st.first + st.count; ++k) {
       const Elim& e = P.elims[k];
-      ds.ws_stride = std::max<long long>(ds.ws_stride, e.kind == K_FINAL ? 3LL * e.b * e.b
-                                                                          : (long long)e.n * e.s + (long long)e.b * e.n);
+      ds.ws_stride = std::max<long long>(ds.ws_stride, e.kind == K_FINAL ? 3LL * e.b * e.b : elim_ws(e));
       ds.maxn = std::max(ds.maxn, e.n);
     }
     d.stages.push_back(ds);
@@ -474,7 +479,7 @@ hipError_t launch_stage_k(const find_plan_s* plan, const DevState* d, int k, Sta
   const DevStage& s2 = d->stages[k];
   a.elims = s2.d_elims; a.n_elims = s2.count; a.ws_stride = s2.ws_stride;
   const long long items = (long long)s2.count * a.nE;
-  const long long groups = (long long)d->slots * groups_per_slot(tc);
+  const long long groups = stage_grid_groups(d->slots, tc);
   const int grid = int(std::min<long long>(items, groups));
   if (grid < 1) return hipSuccess;
   if (s2.phase == PH_FINAL) return launch_final_tc(a, o, s2.maxn, tc, grid, st);

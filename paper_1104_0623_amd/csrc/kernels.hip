@@ -11,18 +11,26 @@
 //   2. LU-factors the tall block [A(S,S); A(B,S)] with partial pivoting over
 //      the S rows only (register-resident panels, MFMA trailing updates); the
 //      B rows of the result hold L21 = A(B,S) U11^{-1},
-//   3. forms L = A(B,S) A(S,S)^{-1} = L21 L11^{-1} P^T (eq. (express-L)),
-//   4. computes [U | W] = [A(B,B) | Sigma(B,:)] - L [A(S,B) | Sigma(S,:)]
-//      (eq. (major-update); W = [-L, I] Sigma), and
-//   5. R = W(:,B) - W(:,S) L^dagger, which equals eq. (gless-update-rule)
-//      Sigma(B,B) - L Sigma(S,B) - Sigma(B,S) L^dagger + L Sigma(S,S) L^dagger.
-// The row permutation P is never applied to A(S,B) or Sigma: the products
-// read row perm[k] for the k-th pivot instead.
+//   3. forms L = A(B,S) A(S,S)^{-1} = L21 L11^{-1} P (eq. (express-L)),
+//      written with its columns in the front's S order,
+//   4. computes U = A(B,B) - L A(S,B) (eq. (major-update)), and
+//   5. R of eq. (gless-update-rule), Sigma(B,B) - L Sigma(S,B)
+//      - Sigma(B,S) L^dagger + L Sigma(S,S) L^dagger, as
+//      R = W(:,B) - W(:,S) L^dagger with W = [-L, I] Sigma.  Sigma_g vanishes
+//      outside the rows and columns of the nodes that carry Sigma<; the plan
+//      puts the q eliminated ones (S_q) first in S, so W(:,S) = 0 outside S_q,
+//      and the kernel forms W_q = W(:,S_q) = Sigma(B,S_q) - L_q Sigma(S_q,S_q)
+//      and R = Sigma(B,B) - [L_q | W_q] [Sigma(S_q,B) ; L_q^dagger], with
+//      L_q = L(:,S_q) (the Sigma(S_q,B) half is skipped when no kept node
+//      carries Sigma<).
+// The row permutation P is never applied to the front: the LU reads row
+// perm[k] for the k-th pivot, and the L solve stores column k at perm[k].
 // Complex products run on v_mfma_f64_16x16x4_f64 as four real products
 // (re*re - im*im, re*im + im*re).
 #include "kernels.hpp"
 
 #include <climits>
+#include <type_traits>
 
 namespace findmi {
 
@@ -89,8 +97,16 @@ struct Orig {
   }
 };
 
+// Operand chunks of the 64x64 workgroup-tile products (gemm_wg): two
+// buffers of an A chunk (8 k x 64 rows) and a B chunk (64 columns x 8 k, rows
+// padded to 9 so that the 16 lanes reading one k of 16 columns hit distinct
+// banks).
+struct WgLds { double2 a[2][8][64]; double2 b[2][64][9]; };
+struct NoWgLds {};
+
 // Shared memory of one workgroup of NT threads working on fronts of at most
-// MAXN nodes.
+// MAXN nodes.  Four-wave workgroups on fronts of at most 512 nodes also hold
+// the workgroup-tile staging buffers (three such workgroups fit one CU).
 template <int NT, int MAXN>
 struct LdsT {
   static constexpr int kNT = NT, kW = NT / 64;
@@ -103,7 +119,10 @@ struct LdsT {
   double2 candrow[2][kW][16];
   double2 tri[16 * 16];
   double2 tinv[16 * 16];
+  typename std::conditional<(NT == 256 && MAXN <= 512), WgLds, NoWgLds>::type wg;
 };
+template <class LDS>
+constexpr bool has_wg() { return std::is_same<decltype(LDS::wg), WgLds>::value; }
 
 // Entries of the assembled front A_g / Sigma_g of one elimination, by front
 // row/column (local [S ; B] index): the block of a source cluster's stored U
@@ -292,17 +311,127 @@ __device__ __forceinline__ void gemm_sub(int M, int N, int K, LA loadA, LB loadB
   else gemm_tiles<NT, false, 2, 2, false>(M, N, K, 0, loadA, loadB, loadC, storeC);
 }
 
+// C(M x N) <- Cinit - A(M x K) B(K x N), complex FP64, with 64x64 workgroup
+// tiles: the four waves of a 256-thread workgroup stage A (64 x 8) and B
+// (8 x 64) chunks through LDS (double-buffered, one barrier per chunk) and
+// each wave computes one 32x32 quarter of the tile on MFMA.  Every entry sees
+// the same MFMA sequence as with 32x32 wave tiles, so the two give identical
+// results; the operand traffic per output is half.  tri as in gemm_tiles, at
+// the granularity of the workgroup tile.  All threads of the workgroup call it.
+template <class LA, class LB, class LC, class SC>
+__device__ __forceinline__ void gemm_wg(WgLds& S, int M, int N, int K, int tri, LA loadA, LB loadB, LC loadC,
+                                        SC storeC) {
+  typedef MfmaT<false> T;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave & 1, wc = wave >> 1;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int tm = (M + 63) >> 6, tn = (N + 63) >> 6;
+  const int nc = (K + 7) >> 3;
+  // staged elements of this thread: A (row ar, k ak and ak + 4), B (k bk,
+  // columns bc and bc + 32); consecutive threads walk A down a column and B
+  // along k, the contiguous directions of the operands
+  const int ar = tid & 63, ak = tid >> 6;
+  const int bk = tid & 7, bc = tid >> 3;
+  for (int t = 0; t < tm * tn; ++t) {
+    const int r0 = (t % tm) * 64, c0 = (t / tm) * 64;
+    if (c0 + 64 <= tri && c0 >= r0 + 64) continue;
+    d4 acc[2][2][2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[h][i][j][q] = 0;
+    double2 ra[2], rb[2];
+    auto gload = [&](int kc) {
+      const int k0 = kc * 8;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int r = r0 + ar, k = k0 + ak + 4 * u;
+        ra[u] = (r < M && k < K) ? loadA(r, k) : zero2();
+        const int c = c0 + bc + 32 * u, kb = k0 + bk;
+        rb[u] = (c < N && kb < K) ? loadB(kb, c) : zero2();
+      }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        S.a[buf][ak + 4 * u][ar] = ra[u];
+        S.b[buf][bc + 32 * u][bk] = rb[u];
+      }
+    };
+    __syncthreads();   // readers of the previous tile's last chunk are done
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int kc = 0; kc < nc; ++kc) {
+      const int buf = kc & 1;
+      if (kc + 1 < nc) gload(kc + 1);
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
+        double aR[2], aI[2], bR[2], bI[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const double2 v = S.a[buf][4 * ks + lk][32 * wr + 16 * i + lr];
+          aR[i] = v.x; aI[i] = v.y;
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const double2 v = S.b[buf][32 * wc + 16 * j + lr][4 * ks + lk];
+          bR[j] = v.x; bI[j] = v.y;
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            acc[0][i][j] = T::mac(aR[i], bR[j], acc[0][i][j]);
+            acc[1][i][j] = T::mac(aR[i], bI[j], acc[1][i][j]);
+          }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            acc[0][i][j] = T::mac(-aI[i], bI[j], acc[0][i][j]);
+            acc[1][i][j] = T::mac(aI[i], bR[j], acc[1][i][j]);
+          }
+      }
+      if (kc + 1 < nc) lstore(buf ^ 1);
+      __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = r0 + 32 * wr + 16 * i + T::drow(q, lk), c = c0 + 32 * wc + 16 * j + lr;
+          if (r < M && c < N) {
+            const double2 v = loadC(r, c);
+            storeC(r, c, make_double2(v.x - acc[0][i][j][q], v.y - acc[1][i][j][q]));
+          }
+        }
+  }
+}
+
 // The Schur-complement products of an elimination, with the wave tile picked
 // per stage (TC: 0 = 32x32, 1 = 32x16, 2 = 16x32, 3 = 16x16; 16-wide where N
 // <= 16) and the 4M or 3M real split of the complex product (C3).  The tile
 // only decides which wave computes which output block: every entry sees the
 // same k-order, so the result does not depend on TC.
-template <int NT, bool F32, int TC, bool C3, class LA, class LB, class LC, class SC>
-__device__ __forceinline__ void gemm_schur(int M, int N, int K, int tri, LA loadA, LB loadB, LC loadC, SC storeC) {
-  constexpr int TM = (TC == 0 || TC == 1) ? 2 : 1;
-  constexpr int TN = (TC == 0 || TC == 2) ? 2 : 1;
-  if (TN == 2 && N <= 16) gemm_tiles<NT, F32, TM, 1, C3>(M, N, K, tri, loadA, loadB, loadC, storeC);
-  else gemm_tiles<NT, F32, TM, TN, C3>(M, N, K, tri, loadA, loadB, loadC, storeC);
+template <int NT, bool F32, int TC, bool C3, class LDS, class LA, class LB, class LC, class SC>
+__device__ __forceinline__ void gemm_schur(LDS& L, int M, int N, int K, int tri, LA loadA, LB loadB, LC loadC,
+                                           SC storeC) {
+  if constexpr (TC == kTileWg && !F32 && !C3 && has_wg<LDS>()) {
+    gemm_wg(L.wg, M, N, K, tri, loadA, loadB, loadC, storeC);
+  } else {
+    // (the workgroup tile has an FP64 4M form only; others take 32x32 wave tiles)
+    constexpr int TM = (TC == 0 || TC == 1 || TC == kTileWg) ? 2 : 1;
+    constexpr int TN = (TC == 0 || TC == 2 || TC == kTileWg) ? 2 : 1;
+    if (TN == 2 && N <= 16) gemm_tiles<NT, F32, TM, 1, C3>(M, N, K, tri, loadA, loadB, loadC, storeC);
+    else gemm_tiles<NT, F32, TM, TN, C3>(M, N, K, tri, loadA, loadB, loadC, storeC);
+  }
 }
 
 // Inverse of the w x w unit-lower triangle held below the diagonal of L.tri
@@ -390,7 +519,7 @@ __device__ __forceinline__ int prow(const int* pm, int s, int r) { return r < s 
 // block's earlier panels, factored in registers (rows spread over the
 // threads), and their U rows formed; the rest of the matrix gets one
 // MFMA trailing update per outer block.  Returns true if a zero pivot was met.
-template <int RPT, int NB, class LDS>
+template <int RPT, int NB, bool WG, class LDS>
 __device__ __forceinline__ bool tall_lu(LDS& L, double2* FA, int n, int s) {
   constexpr int NT = LDS::kNT;
   constexpr int NB2 = 32;
@@ -520,29 +649,33 @@ __device__ __forceinline__ bool tall_lu(LDS& L, double2* FA, int n, int s) {
     }
     // (e) trailing update of rows KE..n, columns KE..s with the block's L and U
     if (KE < s) {
-      gemm_sub<NT>(n - KE, s - KE, KE - K0,
-               [=](int r, int k) { return FA[(size_t)(K0 + k) * n + prow(pm, s, KE + r)]; },
-               [=](int k, int c) { return FA[(size_t)(KE + c) * n + pm[K0 + k]]; },
-               [=](int r, int c) { return FA[(size_t)(KE + c) * n + prow(pm, s, KE + r)]; },
-               [=](int r, int c, double2 v) { FA[(size_t)(KE + c) * n + prow(pm, s, KE + r)] = v; });
+      auto la = [=](int r, int k) { return FA[(size_t)(K0 + k) * n + prow(pm, s, KE + r)]; };
+      auto lb = [=](int k, int c) { return FA[(size_t)(KE + c) * n + pm[K0 + k]]; };
+      auto lc = [=](int r, int c) { return FA[(size_t)(KE + c) * n + prow(pm, s, KE + r)]; };
+      auto sc = [=](int r, int c, double2 v) { FA[(size_t)(KE + c) * n + prow(pm, s, KE + r)] = v; };
+      if constexpr (WG && has_wg<LDS>()) gemm_wg(L.wg, n - KE, s - KE, KE - K0, 0, la, lb, lc, sc);
+      else gemm_sub<NT>(n - KE, s - KE, KE - K0, la, lb, lc, sc);
       __syncthreads();
     }
   }
   return singular;
 }
 
-// X L11 = L21 in place (X -> FA rows s..n, columns 0..s); L11 unit lower.
+// X L11 = L21 for X = L21 L11^{-1} (L11 unit lower, L21 in FA rows s..n,
+// columns 0..s, both in pivot order), stored as Lo(:, perm[k]) = X(:, k)
+// (Lo is b x s with leading dimension b): Lo = X P = A(B,S) A(S,S)^{-1} with
+// its columns in the front's S order.  FA rows s..n are overwritten.
 template <class LDS>
-__device__ __forceinline__ void trsm_right_unit_lower(LDS& L, double2* FA, int n, int s, int b) {
+__device__ __forceinline__ void trsm_right_unit_lower(LDS& L, double2* FA, double2* Lo, int n, int s, int b) {
   constexpr int NT = LDS::kNT;
   const int tid = threadIdx.x;
   const int nblk = (s + 15) / 16;
+  const int* pm = L.perm;
   for (int J = nblk - 1; J >= 0; --J) {
     const int j0 = 16 * J, j1 = min(s, j0 + 16), w = j1 - j0;
     if (j1 < s) {
-      const int* pm = L.perm;
       gemm_sub<NT>(b, w, s - j1,
-               [=](int r, int k) { return FA[(size_t)(j1 + k) * n + s + r]; },
+               [=](int r, int k) { return Lo[(size_t)pm[j1 + k] * b + r]; },
                [=](int k, int c) { return FA[(size_t)(j0 + c) * n + pm[j1 + k]]; },
                [=](int r, int c) { return FA[(size_t)(j0 + c) * n + s + r]; },
                [=](int r, int c, double2 v) { FA[(size_t)(j0 + c) * n + s + r] = v; });
@@ -550,7 +683,7 @@ __device__ __forceinline__ void trsm_right_unit_lower(LDS& L, double2* FA, int n
     {
       for (int t = tid; t < 256; t += NT) {
         const int i = t >> 4, jj = t & 15;
-        L.tri[t] = (i < w && jj < w) ? FA[(size_t)(j0 + jj) * n + L.perm[j0 + i]] : zero2();
+        L.tri[t] = (i < w && jj < w) ? FA[(size_t)(j0 + jj) * n + pm[j0 + i]] : zero2();
       }
     }
     __syncthreads();
@@ -561,14 +694,14 @@ __device__ __forceinline__ void trsm_right_unit_lower(LDS& L, double2* FA, int n
                [=](int r, int k) { return FA[(size_t)(j0 + k) * n + s + r]; },
                [=](int k, int c) { double2 v = LL->tinv[k * 16 + c]; return make_double2(-v.x, -v.y); },
                [=](int r, int c) { return zero2(); },
-               [=](int r, int c, double2 v) { FA[(size_t)(j0 + c) * n + s + r] = v; });
+               [=](int r, int c, double2 v) { Lo[(size_t)pm[j0 + c] * b + r] = v; });
     }
     __syncthreads();
   }
 }
 
 template <int RPT, int TC, int CM, int NT, int MAXN>
-__global__ __launch_bounds__(NT, 3) void k_stage(StageArgs a) {
+__global__ __launch_bounds__(NT, TC == kTileWg ? 2 : 3) void k_stage(StageArgs a) {
   constexpr int NB = 16 / RPT;  // panel columns held in registers
   __shared__ LdsT<NT, MAXN> L;
   const int tid = threadIdx.x;
@@ -578,7 +711,8 @@ __global__ __launch_bounds__(NT, 3) void k_stage(StageArgs a) {
     const int ei = int(item / a.nE), e = int(item % a.nE);
     const ElimDev E = a.elims[ei];
     const int s = E.s, b = E.b, n = E.n;
-    double2* W = FA + (size_t)n * s;   // FA: tall block n x s; W: b x n
+    double2* Lo = FA + (size_t)n * s;  // FA: tall block n x s; Lo: L (b x s, front column order)
+    double2* W = Lo + (size_t)b * s;   // W_q = W(:, S_q) (b x q)
     double2* pool = a.pool + (size_t)e * a.pool_stride;
     for (int k = tid; k < n; k += NT) {
       const int g = a.map_node[E.map + k];
@@ -597,43 +731,45 @@ __global__ __launch_bounds__(NT, 3) void k_stage(StageArgs a) {
     __syncthreads();
     // 2. tall LU, 3. L = L21 L11^{-1}
     if (s > 0) {
-      if (tall_lu<RPT, NB>(L, FA, n, s) && tid == 0) a.status[e] = 1;
-      trsm_right_unit_lower(L, FA, n, s, b);
+      if (tall_lu<RPT, NB, TC == kTileWg>(L, FA, n, s) && tid == 0) a.status[e] = 1;
+      trsm_right_unit_lower(L, FA, Lo, n, s, b);
     }
-    // 4. [U | W] = [A(B,B) | Sigma(B,:)] - L [A(perm,B) | Sigma(perm,:)]
-    // 5. R = W(:, B) - W(:, perm) L^dagger
-    // (FP32 products in the mixed form, FP64 otherwise)
+    // 4. U = A(B,B) - L A(S,B); 5. W_q and R (FP32 products in the mixed form,
+    // FP64 otherwise)
     double2* Uo = pool + E.dst;
     double2* Ro = Uo + (size_t)b * b;
-    const int* perm = L.perm;
-    auto l_ = [=](int r, int k) { return FA[(size_t)k * n + s + r]; };
-    auto b1 = [=](int k, int c) { return c < b ? fr.a(perm[k], s + c) : fr.s(perm[k], c - b); };
-    auto c1 = [=](int r, int c) { return c < b ? fr.a(s + r, s + c) : fr.s(s + r, c - b); };
-    auto s1 = [=](int r, int c, double2 v) { if (c < b) Uo[(size_t)c * b + r] = v; else W[(size_t)(c - b) * b + r] = v; };
-    auto a2 = [=](int r, int k) { return W[(size_t)perm[k] * b + r]; };
-    auto b2 = [=](int k, int c) { return conjd(FA[(size_t)k * n + s + c]); };
-    auto c2 = [=](int r, int c) { return W[(size_t)(s + c) * b + r]; };
-    auto s2 = [=](int r, int c, double2 v) { Ro[(size_t)c * b + r] = v; };
+    const int q = E.ssig, q0 = E.bsig ? E.ssig : 0;
+    auto lo_ = [=](int r, int k) { return Lo[(size_t)k * b + r]; };
+    auto bu = [=](int k, int c) { return fr.a(k, s + c); };
+    auto cu = [=](int r, int c) { return fr.a(s + r, s + c); };
+    auto su = [=](int r, int c, double2 v) { Uo[(size_t)c * b + r] = v; };
+    auto bw = [=](int k, int c) { return fr.s(k, c); };
+    auto cw = [=](int r, int c) { return fr.s(s + r, c); };
+    auto sw = [=](int r, int c, double2 v) { W[(size_t)c * b + r] = v; };
+    // R = Sigma(B,B) - [L_q | W_q] [Sigma(S_q,B) ; L_q^dagger] (first half only when q0 = q)
+    auto ar = [=](int r, int k) { return k < q0 ? Lo[(size_t)k * b + r] : W[(size_t)(k - q0) * b + r]; };
+    auto br = [=](int k, int c) { return k < q0 ? fr.s(k, s + c) : conjd(Lo[(size_t)(k - q0) * b + c]); };
+    auto cr = [=](int r, int c) { return fr.s(s + r, s + c); };
+    auto sr = [=](int r, int c, double2 v) { Ro[(size_t)c * b + r] = v; };
     // with a.sym, U is complex symmetric and R anti-Hermitian: their tiles
     // above the diagonal are not formed, and every reader of U and R takes
     // an upper entry from its mirror below the diagonal
     const int tri = a.sym ? b : 0;
-    if (E.rzero) {
-      // Sigma< vanishes on this front: R = 0, and only U = A(B,B) - L A(perm,B) is formed
-      for_each_rc<NT>(b, b, [&](int r, int c) { Ro[(size_t)c * b + r] = zero2(); });
-      if (E.f32) gemm_schur<NT, true, TC, CM == 1>(b, b, s, tri, l_, b1, c1, s1);
-      else gemm_schur<NT, false, TC, CM == 1>(b, b, s, tri, l_, b1, c1, s1);
-    } else if (E.f32) {
-      gemm_schur<NT, true, TC, CM == 1>(b, b + n, s, tri, l_, b1, c1, s1);
-      __syncthreads();
-      gemm_schur<NT, true, TC, CM == 1>(b, b, s, tri, a2, b2, c2, s2);
-    } else {
-      gemm_schur<NT, false, TC, CM == 1>(b, b + n, s, tri, l_, b1, c1, s1);
-      __syncthreads();
-      gemm_schur<NT, false, TC, CM == 1>(b, b, s, tri, a2, b2, c2, s2);
-    }
+    auto products = [&](auto f32) {
+      constexpr bool F = decltype(f32)::value;
+      gemm_schur<NT, F, TC, CM == 1>(L, b, b, s, tri, lo_, bu, cu, su);
+      if (E.rzero) {
+        // Sigma< vanishes on this front: R = 0
+        for_each_rc<NT>(b, b, [&](int r, int c) { Ro[(size_t)c * b + r] = zero2(); });
+      } else {
+        if (q > 0) gemm_schur<NT, F, TC, CM == 1>(L, b, q, q, 0, lo_, bw, cw, sw);
+        __syncthreads();
+        gemm_schur<NT, F, TC, CM == 1>(L, b, b, q0 + q, tri, ar, br, cr, sr);
+      }
+    };
+    if (E.f32) products(std::true_type{});
+    else products(std::false_type{});
     __syncthreads();
-
   }
 }
 
@@ -668,11 +804,9 @@ __global__ __launch_bounds__(NT, 3) void k_final(StageArgs a, OutArgs o) {
                                      : make_double2(r - bp == c ? 1.0 : 0.0, 0.0);
     });
     __syncthreads();
-    if (tall_lu<RPT, NB>(L, FA, n, bp) && tid == 0) a.status[e] = 1;
-    trsm_right_unit_lower(L, FA, n, bp, bp);
-    // G(:, perm[k]) = L(:, k)
-    for_each_rc<NT>(bp, bp, [&](int i, int k) { G[(size_t)L.perm[k] * bp + i] = FA[(size_t)k * n + bp + i]; });
-    __syncthreads();
+    if (tall_lu<RPT, NB, false>(L, FA, n, bp) && tid == 0) a.status[e] = 1;
+    // G(:, perm[k]) = L(:, k): the L solve of the identity rows stores U_K^{-1}
+    trsm_right_unit_lower(L, FA, G, n, bp, bp);
     // T = R_K G^dagger   (gemm_sub returns 0 - R G^dagger)
     const int sym = a.sym;
     gemm_sub<NT>(bp, bp, bp,
@@ -730,13 +864,14 @@ __global__ __launch_bounds__(NT, 3) void k_final(StageArgs a, OutArgs o) {
 // build in parallel.
 #define FIND_LAUNCH_STAGE(R, T, C)                                                            \
   if (tc == T && cm == C) {                                                                   \
-    hipLaunchKernelGGL((k_stage<R, T, C, kThreads, kMaxFront>), dim3(grid), dim3(kThreads), 0, st, a); \
+    hipLaunchKernelGGL((k_stage<R, T, C, kThreads, kThreads * R>), dim3(grid), dim3(kThreads), 0, st, a); \
     return hipGetLastError();                                                                 \
   }
 #if FIND_TU == 1 || FIND_TU == 2
 hipError_t FIND_CAT(launch_stage_r, FIND_TU)(const StageArgs& a, int tc, int cm, int grid, hipStream_t st) {
   FIND_LAUNCH_STAGE(FIND_TU, 0, 0) FIND_LAUNCH_STAGE(FIND_TU, 1, 0) FIND_LAUNCH_STAGE(FIND_TU, 2, 0) FIND_LAUNCH_STAGE(FIND_TU, 3, 0)
   FIND_LAUNCH_STAGE(FIND_TU, 0, 1) FIND_LAUNCH_STAGE(FIND_TU, 1, 1) FIND_LAUNCH_STAGE(FIND_TU, 2, 1) FIND_LAUNCH_STAGE(FIND_TU, 3, 1)
+  FIND_LAUNCH_STAGE(FIND_TU, kTileWg, 0) FIND_LAUNCH_STAGE(FIND_TU, kTileWg, 1)
   return hipErrorInvalidValue;
 }
 #endif
@@ -776,10 +911,10 @@ hipError_t launch_stage_w2(const StageArgs& a, int rpt, int cm, int grid, hipStr
 #if FIND_TU == 4
 hipError_t launch_final(const StageArgs& a, const OutArgs& o, int rpt, int grid, hipStream_t st) {
   switch (rpt) {
-    case 1: hipLaunchKernelGGL((k_final<1, kThreads, kMaxFront>), dim3(grid), dim3(kThreads), 0, st, a, o); break;
-    case 2: hipLaunchKernelGGL((k_final<2, kThreads, kMaxFront>), dim3(grid), dim3(kThreads), 0, st, a, o); break;
-    case 4: hipLaunchKernelGGL((k_final<4, kThreads, kMaxFront>), dim3(grid), dim3(kThreads), 0, st, a, o); break;
-    case 8: hipLaunchKernelGGL((k_final<8, kThreads, kMaxFront>), dim3(grid), dim3(kThreads), 0, st, a, o); break;
+    case 1: hipLaunchKernelGGL((k_final<1, kThreads, kThreads * 1>), dim3(grid), dim3(kThreads), 0, st, a, o); break;
+    case 2: hipLaunchKernelGGL((k_final<2, kThreads, kThreads * 2>), dim3(grid), dim3(kThreads), 0, st, a, o); break;
+    case 4: hipLaunchKernelGGL((k_final<4, kThreads, kThreads * 4>), dim3(grid), dim3(kThreads), 0, st, a, o); break;
+    case 8: hipLaunchKernelGGL((k_final<8, kThreads, kThreads * 8>), dim3(grid), dim3(kThreads), 0, st, a, o); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -15,6 +15,8 @@ struct ElimDev {
   int aux;                // final leaf block: index of its output record
   int f32;                // 1: Schur/Sigma products in FP32 (mixed form)
   int rzero;              // 1: Sigma< vanishes on the front: R = 0, only U is formed
+  int ssig;               // eliminated nodes carrying Sigma< (the first ssig of S)
+  int bsig;               // 1: some kept node carries Sigma<
 };
 
 struct LeafOutDev { int elim_dst_lo, elim_dst_hi, bprime, n_nodes, node_first, bond_first, n_bonds, pad; };
@@ -59,16 +61,25 @@ constexpr int kThreads = 256;
 // Stage launchers (one per kernel family; see kernels.hip).  tc: wave tile of
 // the Schur products (0..3; families with 4 or 8 panel rows per thread take
 // tc = 0 only), kTileWave: one 64-thread workgroup (a single wave) per front,
-// for stages whose fronts have at most kWaveMaxFront nodes, or kTileTwoWave:
+// for stages whose fronts have at most kWaveMaxFront nodes, kTileTwoWave:
 // one 128-thread workgroup per front (fronts of at most kTwoWaveMaxFront
-// nodes).  cm: 0 = 4M, 1 = 3M complex products.
-constexpr int kTileConfigs = 6;
+// nodes), or kTileWg: 64x64 workgroup tiles whose operands the four waves
+// share through LDS (Schur products and LU trailing updates; fronts of at
+// most 512 nodes).  cm: 0 = 4M, 1 = 3M complex products.
+constexpr int kTileConfigs = 7;
 constexpr int kTileWave = 4;       // one wave (64 threads) per front
 constexpr int kTileTwoWave = 5;    // two waves (128 threads) per front
+constexpr int kTileWg = 6;         // 64x64 workgroup tiles staged through LDS
 constexpr int kWaveMaxFront = 128;
 constexpr int kTwoWaveMaxFront = 256;
 // workgroups resident where one 256-thread workgroup is, for a configuration
 inline int groups_per_slot(int tc) { return tc == kTileWave ? 4 : tc == kTileTwoWave ? 2 : 1; }
+// workgroups a stage launches with configuration tc on a device with `slots`
+// 256-thread slots (three per CU); the workgroup-tile form is compiled for
+// two workgroups per CU
+inline long long stage_grid_groups(long long slots, int tc) {
+  return tc == kTileWg ? slots * 2 / 3 : slots * groups_per_slot(tc);
+}
 #define FIND_CAT_(a, b) a##b
 #define FIND_CAT(a, b) FIND_CAT_(a, b)
 hipError_t launch_stage_r1(const StageArgs& a, int tc, int cm, int grid, hipStream_t st);
@@ -84,7 +95,7 @@ inline int wave_rpt(int n) { return n <= 64 ? 1 : 2; }
 inline int wave2_rpt(int n) { return n <= 128 ? 1 : 2; }
 // bit mask of the tile configurations a stage with fronts of at most maxn nodes has
 inline int stage_tile_mask(int maxn, bool final_stage) {
-  int m = final_stage ? 1 : (panel_rpt(maxn) <= 2 ? 0xf : 1);
+  int m = final_stage ? 1 : (panel_rpt(maxn) <= 2 ? (0xf | 1 << kTileWg) : 1);
   if (maxn <= kWaveMaxFront) m |= 1 << kTileWave;
   if (maxn <= kTwoWaveMaxFront) m |= 1 << kTileTwoWave;
   return m;

@@ -42,14 +42,20 @@ int count_bonds(int Nx, int Ny, int stencil) {
 }
 
 double elim_flops(const Elim& e, bool symmetric) {
-  double s = e.s, b = e.b;
+  double s = e.s, b = e.b, q = e.ssig;
   if (e.kind == K_FINAL) return 8.0 * 2.0 * s * s * s;
-  // with U complex symmetric and R anti-Hermitian only half of U = A(B,B) - L A(S,B)
-  // and of R = W(:,B) - W(:,S) L^dagger is formed: s b^2 fewer multiply-adds.
-  // With R = 0 (no Sigma< in the front) W and R are not formed: LU s^3/3 + s^2 b / 2,
-  // L s^2 b / 2, U s b^2 (half of it when symmetric)
-  if (e.rzero) return 8.0 * (s * s * s / 3.0 + s * s * b + (symmetric ? 0.5 : 1.0) * s * b * b);
-  return 8.0 * (s * s * s / 3.0 + 2.0 * s * s * b + (symmetric ? 2.0 : 3.0) * s * b * b);
+  // complex multiply-adds: LU s^3/3 + s^2 b / 2, L s^2 b / 2, U = A(B,B) - L A(S,B)
+  // s b^2.  Sigma_g is supported on the q eliminated nodes that carry Sigma< (and
+  // the kept ones): W_q = Sigma(B,S_q) - L_q Sigma(S_q,S_q) costs b q^2 and
+  // R = Sigma(B,B) - [L_q | W_q] [Sigma(S_q,B) ; L_q^dagger] costs 2 q b^2 (q b^2
+  // when no kept node carries Sigma<, so that Sigma(S_q,B) = 0).  With U complex
+  // symmetric and R anti-Hermitian only half of U and of R is formed.  With
+  // R = 0 (no Sigma< in the front) W and R are not formed.
+  const double h = symmetric ? 0.5 : 1.0;
+  const double base = s * s * s / 3.0 + s * s * b + h * s * b * b;
+  if (e.rzero) return 8.0 * base;
+  const double q0 = e.bsig ? q : 0.0;
+  return 8.0 * (base + b * q * q + h * b * b * (q0 + q));
 }
 
 namespace {
@@ -146,15 +152,38 @@ struct Builder {
     return (it != v.end() && *it == x) ? int(it - v.begin()) : -1;
   }
 
+  // R_C = 0 for an upward-pass cluster away from both contact columns: Sigma<
+  // is supported on the contact columns y = 0 and y = Ny - 1 only, so
+  // Sigma<(C, C) = 0, and so R = 0 for it and (recursively) for all its
+  // descendants
+  bool up_rzero(const Cluster& c) const { return c.r.y0 > 0 && c.r.y0 + c.r.h < Ny; }
+
   // Emit an elimination whose assembled node list is `list` (with per-entry
   // source and source position) and whose kept set is `keep` (in this order).
+  // sig_src[k][p]: the row of source k's stored R at position p may be
+  // non-zero (null: source k has none).  An entry carries Sigma< (its row and
+  // column of Sigma_g may be non-zero) if its source row does, or if it comes
+  // from the original matrix and lies on a contact column; the eliminated
+  // entries that carry it are placed first in S.  out_sig receives, per kept
+  // node, whether its row of the resulting R may be non-zero: every row when
+  // an eliminated node carries Sigma< (the L Sigma(S,S) L^dagger terms fill
+  // R), else the rows of the kept nodes that carry it (R = Sigma_g(B,B)).
   std::string emit(const std::vector<int>& list, const std::vector<int>& src,
-                   const std::vector<int>& pos, const std::vector<int>& keep, Elim e) {
+                   const std::vector<int>& pos, const std::vector<int>& keep, Elim e,
+                   const std::vector<char>* const sig_src[2], std::vector<char>* out_sig = nullptr) {
     std::vector<int> keep_sorted = keep;
     std::sort(keep_sorted.begin(), keep_sorted.end());
     std::vector<int> S_idx, in_list(keep.size(), -1);
     for (size_t k = 0; k < list.size(); ++k)
       if (find_sorted(keep_sorted, list[k]) < 0) S_idx.push_back(int(k));
+    auto carries = [&](int k) -> bool {
+      if (src[k] == SRC0 || src[k] == SRC1) return sig_src[src[k]] && (*sig_src[src[k]])[pos[k]];
+      const int y = list[k] / Nx;
+      return y == 0 || y == Ny - 1;
+    };
+    const auto mid = std::stable_partition(S_idx.begin(), S_idx.end(), carries);
+    e.ssig = e.rzero ? 0 : int(mid - S_idx.begin());
+    e.bsig = 0;
     // kept nodes in `keep` order, located in the list
     std::vector<int> listpos_sorted(list.size());
     std::iota(listpos_sorted.begin(), listpos_sorted.end(), 0);
@@ -169,6 +198,12 @@ struct Builder {
         return buf;
       }
       in_list[q] = *it;
+      if (!e.rzero && carries(*it)) e.bsig = 1;
+    }
+    if (out_sig) {
+      out_sig->assign(keep.size(), 0);
+      if (!e.rzero)
+        for (size_t q = 0; q < keep.size(); ++q) (*out_sig)[q] = (e.ssig > 0 || carries(in_list[q])) ? 1 : 0;
     }
     e.s = int(S_idx.size());
     e.b = int(keep.size());
@@ -224,10 +259,8 @@ struct Builder {
         Cluster& c = P.cl[q];
         if (c.height != h) continue;
         Elim e; e.phase = PH_UP; e.cluster = q; e.level = c.depth; e.dst = c.up_off;
-        // Sigma< is supported on the contact columns y = 0 and y = Ny - 1 only;
-        // a cluster away from both has Sigma<(C, C) = 0, and so R = 0 for it and
-        // (recursively) for all its descendants
-        e.rzero = (c.r.y0 > 0 && c.r.y0 + c.r.h < Ny) ? 1 : 0;
+        e.rzero = up_rzero(c) ? 1 : 0;
+        const std::vector<char>* sig_src[2] = {nullptr, nullptr};
         std::vector<int> list, src, pos;
         if (c.leaf()) {
           list = cluster_nodes(c.r);
@@ -237,9 +270,10 @@ struct Builder {
             const Cluster& ch = P.cl[c.child[k]];
             for (size_t p = 0; p < ch.B.size(); ++p) { list.push_back(ch.B[p]); src.push_back(k); pos.push_back(int(p)); }
             e.src_off[k] = ch.up_off; e.src_ld[k] = int(ch.B.size());
+            sig_src[k] = &ch.up_sig;
           }
         }
-        if (!(err = emit(list, src, pos, c.B, e)).empty()) return err;
+        if (!(err = emit(list, src, pos, c.B, e, sig_src, &c.up_sig)).empty()) return err;
       }
       if (int(P.elims.size()) > first) P.stages.push_back({first, int(P.elims.size()) - first, PH_UP, -1});
     }
@@ -259,7 +293,8 @@ struct Builder {
         }
         for (size_t p = 0; p < D1.B.size(); ++p) { list.push_back(D1.B[p]); src.push_back(SRC1); pos.push_back(int(p)); }
         e.src_off[1] = D1.up_off; e.src_ld[1] = int(D1.B.size());
-        if (!(err = emit(list, src, pos, c.Bc, e)).empty()) return err;
+        const std::vector<char>* sig_src[2] = {c.parent != 0 ? &D.dn_sig : nullptr, &D1.up_sig};
+        if (!(err = emit(list, src, pos, c.Bc, e, sig_src, &c.dn_sig)).empty()) return err;
       }
       if (int(P.elims.size()) > first) P.stages.push_back({first, int(P.elims.size()) - first, PH_DOWN, -1});
     }
@@ -301,7 +336,8 @@ struct Builder {
         std::vector<int> keep = Cn;
         keep.insert(keep.end(), N.begin(), N.end());
         keeps[l] = keep;
-        if (!(err = emit(list, src, pos, keep, e)).empty()) return err;
+        const std::vector<char>* sig_src[2] = {leaves[l] != 0 ? &c.dn_sig : nullptr, nullptr};
+        if (!(err = emit(list, src, pos, keep, e, sig_src)).empty()) return err;
       }
       P.stages.push_back({first, int(P.elims.size()) - first, PH_LEAF, v});
       first = int(P.elims.size());

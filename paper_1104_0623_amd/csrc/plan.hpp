@@ -15,6 +15,8 @@ struct Cluster {
   int depth = 0, height = 0;
   std::vector<int> B;    // boundary set B_C: nodes of C with a pattern-neighbour outside C
   std::vector<int> Bc;   // B_{C-bar}: nodes outside C with a pattern-neighbour in C
+  // per node of B (Bc): 1 if its row of the stored R_C (R_{C-bar}) may be non-zero
+  std::vector<char> up_sig, dn_sig;
   int64_t up_off = -1;   // pool offset of (U_C, R_C)
   int64_t dn_off = -1;   // pool offset of (U_{C-bar}, R_{C-bar})
   bool leaf() const { return child[0] < 0; }
@@ -35,6 +37,12 @@ struct Elim {
   // 1: Sigma< vanishes on every node of the front (an upward-pass cluster that
   // touches neither contact column), so R = 0 and only U is formed
   int rzero = 0;
+  // number of eliminated nodes whose rows of the assembled Sigma_g may be
+  // non-zero; they come first in S, and the rows of Sigma_g of the other
+  // s - ssig eliminated nodes (and their columns) are exactly zero
+  int ssig = 0;
+  // 1: some kept node carries Sigma< (its row of Sigma_g may be non-zero)
+  int bsig = 0;
 };
 
 struct Stage { int first, count, phase, variant; };

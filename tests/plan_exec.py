@@ -31,7 +31,7 @@ def orig_entries(nodes_r, nodes_c, Nx, Ny, Hm, E, sig, sless):
     return A, S
 
 
-def execute(plan_export: dict, Nx, Ny, stencil, Hm, E, sig, sless, want_bonds=True, record=None):
+def execute(plan_export: dict, Nx, Ny, stencil, Hm, E, sig, sless, want_bonds=True, record=None, fronts=None):
     ex = plan_export
     elims, maps, stages = ex["elims"], ex["maps"], ex["stages"]
     variant = 1 if want_bonds else 0
@@ -55,6 +55,8 @@ def execute(plan_export: dict, Nx, Ny, stencil, Hm, E, sig, sless, want_bonds=Tr
                     U, R = pool[off]
                     A[np.ix_(sel, sel)] = U[np.ix_(pos[sel], pos[sel])]
                     S[np.ix_(sel, sel)] = R[np.ix_(pos[sel], pos[sel])]
+            if fronts is not None:
+                fronts[k] = S.copy()
             Sx, Bx = slice(0, s), slice(s, n)
             if s:
                 L = np.linalg.solve(A[Sx, Sx].T, A[Bx, Sx].T).T

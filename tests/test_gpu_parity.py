@@ -126,8 +126,8 @@ def test_singleton_and_one_leaf_meshes():
 
 
 def test_tile_configurations_give_bitwise_equal_results():
-    """Wave tiles only move work between waves (bitwise equal results); the
-    one-wave form may round differently."""
+    """Wave tiles and the workgroup tile only move work between waves (bitwise
+    equal results); the one- and two-wave forms may round differently."""
     f = find()
     E = inputs.energies_linspace(-3.2, 3.1, 5)
     prob = inputs.make_problem(40, 52, 9, vmax=1.0, seed=7, energies=E, fL=1.0, fR=0.2)
@@ -135,11 +135,12 @@ def test_tile_configurations_give_bitwise_equal_results():
     base = f.run_problem(plan, prob, want_bonds=True)
     opts = plan.tile_options()
     assert any(4 in o for o in opts)     # the small-front stages have the one-wave form
-    for tc in (1, 2, 3, 4, 5):
+    assert any(6 in o for o in opts)     # and the workgroup tile
+    for tc in (1, 2, 3, 4, 5, 6):
         plan.set_tiles([tc if tc in o else 0 for o in opts])
         out = f.run_problem(plan, prob, want_bonds=True)
         for k in base:
-            if tc < 4:
+            if tc < 4 or tc == 6:
                 assert np.array_equal(out[k], base[k]), (tc, k)
             else:
                 # the one- and two-wave forms factor fronts of 65..128 (129..256)

@@ -231,7 +231,8 @@ enum {
   FIND_EF_CLUSTER, FIND_EF_PHASE, FIND_EF_LEVEL,
   FIND_EF_RZERO,       /* 1: Sigma< vanishes on the front, so R = 0 (not formed) */
   FIND_EF_SSIG,        /* eliminated nodes carrying Sigma< (the first SSIG of S) */
-  FIND_EF_BSIG,        /* 1: some kept node carries Sigma<                       */
+  FIND_EF_BSIG,        /* 1: some kept node coupled to S carries Sigma<          */
+  FIND_EF_BACT,        /* kept nodes coupled to S (the first BACT of B)          */
   FIND_EF_FIELDS
 };
 /* Phases: 0 upward, 1 downward, 2 leaf extraction, 3 final leaf block.

@@ -150,7 +150,7 @@ find_status ensure_device(find_plan_s* p, DevState** out) {
       d.kind = e.kind; d.s = e.s; d.b = e.b; d.n = e.n;
       d.src0 = std::max<int64_t>(0, e.src_off[0]); d.src1 = std::max<int64_t>(0, e.src_off[1]);
       d.ld0 = e.src_ld[0]; d.ld1 = e.src_ld[1];
-      d.dst = e.dst; d.map = e.map; d.aux = -1; d.rzero = e.rzero; d.ssig = e.ssig; d.bsig = e.bsig;
+      d.dst = e.dst; d.map = e.map; d.aux = -1; d.rzero = e.rzero; d.ssig = e.ssig; d.bsig = e.bsig; d.bact = e.bact;
       // mixed form: FP32 products except the top-level eliminations, large
       // separators and the final leaf blocks, which stay FP64
       const int top = p->opts.fp64_top_levels == 0 ? 2 : p->opts.fp64_top_levels;
@@ -335,7 +335,7 @@ find_status find_plan_export(find_plan plan, int32_t* elims, int32_t* maps, int3
       r[FIND_EF_SRC1] = int32_t(e.src_off[1]); r[FIND_EF_LD1] = e.src_ld[1];
       r[FIND_EF_DST] = int32_t(e.dst); r[FIND_EF_MAP] = e.map;
       r[FIND_EF_CLUSTER] = e.cluster; r[FIND_EF_PHASE] = e.phase; r[FIND_EF_LEVEL] = e.level;
-      r[FIND_EF_RZERO] = e.rzero; r[FIND_EF_SSIG] = e.ssig; r[FIND_EF_BSIG] = e.bsig;
+      r[FIND_EF_RZERO] = e.rzero; r[FIND_EF_SSIG] = e.ssig; r[FIND_EF_BSIG] = e.bsig; r[FIND_EF_BACT] = e.bact;
     }
   if (maps)
     for (size_t k = 0; k < P.map_node.size(); ++k) {

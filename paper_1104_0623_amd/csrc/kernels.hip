@@ -711,8 +711,11 @@ __global__ __launch_bounds__(NT, TC == kTileWg ? 2 : 3) void k_stage(StageArgs a
     const int ei = int(item / a.nE), e = int(item % a.nE);
     const ElimDev E = a.elims[ei];
     const int s = E.s, b = E.b, n = E.n;
-    double2* Lo = FA + (size_t)n * s;  // FA: tall block n x s; Lo: L (b x s, front column order)
-    double2* W = Lo + (size_t)b * s;   // W_q = W(:, S_q) (b x q)
+    // only the first ba kept nodes are coupled to S: the tall block, L, W_q and
+    // the Schur corrections of U and R cover them (na = s + ba rows)
+    const int ba = E.bact, na = s + ba;
+    double2* Lo = FA + (size_t)na * s;  // FA: tall block na x s; Lo: L (ba x s, front column order)
+    double2* W = Lo + (size_t)ba * s;   // W_q = W(:, S_q) (ba x q)
     double2* pool = a.pool + (size_t)e * a.pool_stride;
     for (int k = tid; k < n; k += NT) {
       const int g = a.map_node[E.map + k];
@@ -727,46 +730,55 @@ __global__ __launch_bounds__(NT, TC == kTileWg ? 2 : 3) void k_stage(StageArgs a
                         a.energies[e], a.Nx, a.Ny, a.nst}, a.sym};
     // 1. assemble the tall block [A_g(S,S); A_g(B,S)]; the other blocks of A_g
     //    and all of Sigma_g are gathered from their sources by the products
-    for_each_rc<NT>(n, s, [&](int r, int c) { FA[(size_t)c * n + r] = fr.a(r, c); });
+    for_each_rc<NT>(na, s, [&](int r, int c) { FA[(size_t)c * na + r] = fr.a(r, c); });
     __syncthreads();
     // 2. tall LU, 3. L = L21 L11^{-1}
     if (s > 0) {
-      if (tall_lu<RPT, NB, TC == kTileWg>(L, FA, n, s) && tid == 0) a.status[e] = 1;
-      trsm_right_unit_lower(L, FA, Lo, n, s, b);
+      if (tall_lu<RPT, NB, TC == kTileWg>(L, FA, na, s) && tid == 0) a.status[e] = 1;
+      trsm_right_unit_lower(L, FA, Lo, na, s, ba);
     }
     // 4. U = A(B,B) - L A(S,B); 5. W_q and R (FP32 products in the mixed form,
     // FP64 otherwise)
     double2* Uo = pool + E.dst;
     double2* Ro = Uo + (size_t)b * b;
     const int q = E.ssig, q0 = E.bsig ? E.ssig : 0;
-    auto lo_ = [=](int r, int k) { return Lo[(size_t)k * b + r]; };
+    auto lo_ = [=](int r, int k) { return Lo[(size_t)k * ba + r]; };
     auto bu = [=](int k, int c) { return fr.a(k, s + c); };
     auto cu = [=](int r, int c) { return fr.a(s + r, s + c); };
     auto su = [=](int r, int c, double2 v) { Uo[(size_t)c * b + r] = v; };
     auto bw = [=](int k, int c) { return fr.s(k, c); };
     auto cw = [=](int r, int c) { return fr.s(s + r, c); };
-    auto sw = [=](int r, int c, double2 v) { W[(size_t)c * b + r] = v; };
+    auto sw = [=](int r, int c, double2 v) { W[(size_t)c * ba + r] = v; };
     // R = Sigma(B,B) - [L_q | W_q] [Sigma(S_q,B) ; L_q^dagger] (first half only when q0 = q)
-    auto ar = [=](int r, int k) { return k < q0 ? Lo[(size_t)k * b + r] : W[(size_t)(k - q0) * b + r]; };
-    auto br = [=](int k, int c) { return k < q0 ? fr.s(k, s + c) : conjd(Lo[(size_t)(k - q0) * b + c]); };
+    auto ar = [=](int r, int k) { return k < q0 ? Lo[(size_t)k * ba + r] : W[(size_t)(k - q0) * ba + r]; };
+    auto br = [=](int k, int c) { return k < q0 ? fr.s(k, s + c) : conjd(Lo[(size_t)(k - q0) * ba + c]); };
     auto cr = [=](int r, int c) { return fr.s(s + r, s + c); };
     auto sr = [=](int r, int c, double2 v) { Ro[(size_t)c * b + r] = v; };
     // with a.sym, U is complex symmetric and R anti-Hermitian: their tiles
     // above the diagonal are not formed, and every reader of U and R takes
     // an upper entry from its mirror below the diagonal
-    const int tri = a.sym ? b : 0;
+    const int tri = a.sym ? ba : 0;
     auto products = [&](auto f32) {
       constexpr bool F = decltype(f32)::value;
-      gemm_schur<NT, F, TC, CM == 1>(L, b, b, s, tri, lo_, bu, cu, su);
+      gemm_schur<NT, F, TC, CM == 1>(L, ba, ba, s, tri, lo_, bu, cu, su);
       if (E.rzero) {
         // Sigma< vanishes on this front: R = 0
         for_each_rc<NT>(b, b, [&](int r, int c) { Ro[(size_t)c * b + r] = zero2(); });
       } else {
-        if (q > 0) gemm_schur<NT, F, TC, CM == 1>(L, b, q, q, 0, lo_, bw, cw, sw);
+        if (q > 0) gemm_schur<NT, F, TC, CM == 1>(L, ba, q, q, 0, lo_, bw, cw, sw);
         __syncthreads();
-        gemm_schur<NT, F, TC, CM == 1>(L, b, b, q0 + q, tri, ar, br, cr, sr);
+        gemm_schur<NT, F, TC, CM == 1>(L, ba, ba, q0 + q, tri, ar, br, cr, sr);
       }
     };
+    // rows and columns of the kept nodes not coupled to S: U and R keep the
+    // assembled A_g(B,B) and Sigma_g(B,B) there
+    if (ba < b)
+      for_each_rc<NT>(b, b, [&](int r, int c) {
+        if (r >= ba || c >= ba) {
+          Uo[(size_t)c * b + r] = fr.a(s + r, s + c);
+          if (!E.rzero) Ro[(size_t)c * b + r] = fr.s(s + r, s + c);
+        }
+      });
     if (E.f32) products(std::true_type{});
     else products(std::false_type{});
     __syncthreads();

@@ -16,7 +16,8 @@ struct ElimDev {
   int f32;                // 1: Schur/Sigma products in FP32 (mixed form)
   int rzero;              // 1: Sigma< vanishes on the front: R = 0, only U is formed
   int ssig;               // eliminated nodes carrying Sigma< (the first ssig of S)
-  int bsig;               // 1: some kept node carries Sigma<
+  int bsig;               // 1: some kept node coupled to S carries Sigma<
+  int bact;               // kept nodes coupled to S (the first bact of B)
 };
 
 struct LeafOutDev { int elim_dst_lo, elim_dst_hi, bprime, n_nodes, node_first, bond_first, n_bonds, pad; };

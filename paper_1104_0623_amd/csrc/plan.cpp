@@ -31,6 +31,7 @@
 #include <algorithm>
 #include <array>
 #include <cstdio>
+#include <cstdlib>
 #include <numeric>
 
 namespace findmi {
@@ -51,6 +52,8 @@ double elim_flops(const Elim& e, bool symmetric) {
   // when no kept node carries Sigma<, so that Sigma(S_q,B) = 0).  With U complex
   // symmetric and R anti-Hermitian only half of U and of R is formed.  With
   // R = 0 (no Sigma< in the front) W and R are not formed.
+  // Kept nodes not coupled to S (b - bact of them) take no part in any of it.
+  b = e.bact;
   const double h = symmetric ? 0.5 : 1.0;
   const double base = s * s * s / 3.0 + s * s * b + h * s * b * b;
   if (e.rzero) return 8.0 * base;
@@ -168,9 +171,14 @@ struct Builder {
   // node, whether its row of the resulting R may be non-zero: every row when
   // an eliminated node carries Sigma< (the L Sigma(S,S) L^dagger terms fill
   // R), else the rows of the kept nodes that carry it (R = Sigma_g(B,B)).
+  // With keep_out, the kept nodes coupled to S (a common source, a stencil
+  // bond, or one contact column) are moved ahead of the others, and the
+  // resulting kept order is stored there; otherwise `keep` is used as given.
   std::string emit(const std::vector<int>& list, const std::vector<int>& src,
-                   const std::vector<int>& pos, const std::vector<int>& keep, Elim e,
-                   const std::vector<char>* const sig_src[2], std::vector<char>* out_sig = nullptr) {
+                   const std::vector<int>& pos, const std::vector<int>& keep_in, Elim e,
+                   const std::vector<char>* const sig_src[2], std::vector<char>* out_sig = nullptr,
+                   std::vector<int>* keep_out = nullptr) {
+    std::vector<int> keep = keep_in;
     std::vector<int> keep_sorted = keep;
     std::sort(keep_sorted.begin(), keep_sorted.end());
     std::vector<int> S_idx, in_list(keep.size(), -1);
@@ -199,6 +207,32 @@ struct Builder {
       }
       in_list[q] = *it;
       if (!e.rzero && carries(*it)) e.bsig = 1;
+    }
+    e.bact = int(keep.size());
+    if (keep_out) {
+      auto coupled = [&](int kb) {
+        const int xb = list[kb] % Nx, yb = list[kb] / Nx;
+        for (int ks : S_idx) {
+          if (src[ks] == src[kb] && src[kb] != SRC_ORIG) return true;
+          const int xs = list[ks] % Nx, ys = list[ks] / Nx;
+          const int dx = std::abs(xs - xb), dy = std::abs(ys - yb);
+          if (dx <= 1 && dy <= 1 && (dx + dy == 1 || (stencil == 9 && dx + dy == 2))) return true;
+          if (ys == yb && (ys == 0 || ys == Ny - 1)) return true;
+        }
+        return false;
+      };
+      std::vector<int> order(keep.size());
+      std::iota(order.begin(), order.end(), 0);
+      const auto mid = std::stable_partition(order.begin(), order.end(), [&](int q) { return coupled(in_list[q]); });
+      e.bact = int(mid - order.begin());
+      std::vector<int> k2, l2;
+      for (int q : order) { k2.push_back(keep[q]); l2.push_back(in_list[q]); }
+      keep.swap(k2); in_list.swap(l2);
+      *keep_out = keep;
+      // Sigma(S, B) vanishes on the uncoupled kept nodes: only coupled ones count
+      e.bsig = 0;
+      for (int q = 0; q < e.bact; ++q)
+        if (!e.rzero && carries(in_list[q])) e.bsig = 1;
     }
     if (out_sig) {
       out_sig->assign(keep.size(), 0);
@@ -335,9 +369,8 @@ struct Builder {
         for (int i : Cn) { list.push_back(i); src.push_back(SRC_ORIG); pos.push_back(-1); }
         std::vector<int> keep = Cn;
         keep.insert(keep.end(), N.begin(), N.end());
-        keeps[l] = keep;
         const std::vector<char>* sig_src[2] = {leaves[l] != 0 ? &c.dn_sig : nullptr, nullptr};
-        if (!(err = emit(list, src, pos, keep, e, sig_src)).empty()) return err;
+        if (!(err = emit(list, src, pos, keep, e, sig_src, nullptr, &keeps[l])).empty()) return err;
       }
       P.stages.push_back({first, int(P.elims.size()) - first, PH_LEAF, v});
       first = int(P.elims.size());
@@ -353,12 +386,16 @@ struct Builder {
           P.map_pos.push_back(r % le.b);
         }
         P.elims.push_back(e);
-        // output records: kept order is [C nodes ; N]
+        // output records: the nodes of C at their positions in the kept order
         const Cluster& c = P.cl[leaves[l]];
         LeafOut lo;
         lo.elim = int(P.elims.size()) - 1; lo.variant = v;
         lo.n_nodes = c.r.w * c.r.h; lo.node_first = int(P.outnode_node.size());
-        for (int q2 = 0; q2 < lo.n_nodes; ++q2) { P.outnode_node.push_back(keeps[l][q2]); P.outnode_local.push_back(q2); }
+        for (int q2 = 0; q2 < int(keeps[l].size()); ++q2) {
+          const int nd = keeps[l][q2];
+          if (!inside(c.r, nd % Nx, nd / Nx)) continue;
+          P.outnode_node.push_back(nd); P.outnode_local.push_back(q2);
+        }
         lo.bond_first = int(P.outbonds.size()); lo.n_bonds = 0;
         if (v == 1) {
           std::vector<int> ks = keeps[l];

@@ -43,6 +43,10 @@ struct Elim {
   int ssig = 0;
   // 1: some kept node carries Sigma< (its row of Sigma_g may be non-zero)
   int bsig = 0;
+  // kept nodes coupled to S (the first bact of B): the rows and columns of
+  // A_g and Sigma_g between the other kept nodes and S are exactly zero, so
+  // the elimination leaves their rows and columns of U and R unchanged
+  int bact = 0;
 };
 
 struct Stage { int first, count, phase, variant; };

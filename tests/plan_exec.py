@@ -56,7 +56,7 @@ def execute(plan_export: dict, Nx, Ny, stencil, Hm, E, sig, sless, want_bonds=Tr
                     A[np.ix_(sel, sel)] = U[np.ix_(pos[sel], pos[sel])]
                     S[np.ix_(sel, sel)] = R[np.ix_(pos[sel], pos[sel])]
             if fronts is not None:
-                fronts[k] = S.copy()
+                fronts[k] = (A.copy(), S.copy())
             Sx, Bx = slice(0, s), slice(s, n)
             if s:
                 L = np.linalg.solve(A[Sx, Sx].T, A[Bx, Sx].T).T

@@ -124,7 +124,8 @@ def test_zero_sigma_fronts_are_flagged_exactly(Nx, Ny, stencil, leaf):
         if var == 1:
             continue
         for k in range(first, first + count):
-            kind, s_, b_, q_, q0 = el[k][0], float(el[k][1]), float(el[k][2]), float(el[k][14]), float(el[k][15])
+            kind, s_, q_, q0 = el[k][0], float(el[k][1]), float(el[k][14]), float(el[k][15])
+            b_ = float(el[k][16]) if kind == 0 else float(el[k][2])
             if kind == 1:
                 ok += 16 * s_ ** 3
             elif el[k][13]:
@@ -149,25 +150,34 @@ def test_sigma_support_prefix_is_exact(Nx, Ny, stencil, leaf):
     ex = p.export()
     fronts = {}
     Hm = dense.hamiltonian_matrix(Nx, Ny, prob["H"])
-    execute(ex, Nx, Ny, stencil, Hm, E[0], prob["sigma"][0], prob["sigma_less"][0], want_bonds=True,
-            fronts=fronts)
+    for bonds in (False, True):
+        execute(ex, Nx, Ny, stencil, Hm, E[0], prob["sigma"][0], prob["sigma_less"][0], want_bonds=bonds,
+                fronts=fronts)
     el = ex["elims"]
-    partial = 0
-    for k, Sg in fronts.items():
-        kind, s_, b_, rz, q, bs = el[k][0], el[k][1], el[k][2], el[k][13], el[k][14], el[k][15]
+    partial = inert = 0
+    for k, (Ag, Sg) in fronts.items():
+        kind, s_, b_, rz, q, bs, ba = (el[k][0], el[k][1], el[k][2], el[k][13], el[k][14], el[k][15],
+                                       el[k][16])
         assert kind == 0
+        # kept nodes past the first ba are not coupled to S in A_g or Sigma_g
+        assert 0 <= ba <= b_ and (ba == b_ or el[k][11] == 2), k     # (reordered in leaf extraction only)
+        na = s_ + ba
+        for M in (Ag, Sg):
+            assert np.all(M[na:, :s_] == 0) and np.all(M[:s_, na:] == 0), k
+        inert += b_ - ba
         if rz:
             assert np.all(Sg == 0), k
             continue
         assert 0 <= q <= s_
         assert np.all(Sg[q:s_, :] == 0) and np.all(Sg[:, q:s_] == 0), k
         if not bs:
-            assert np.all(Sg[s_:, :] == 0) and np.all(Sg[:, s_:] == 0), k
+            assert np.all(Sg[s_:na, :s_] == 0) and np.all(Sg[:s_, s_:na] == 0), k
         # the support is tracked per node through the stored R blocks, so it is
         # tight: every eliminated node counted in q has a non-zero row
         assert np.all(np.any(Sg[:q, :] != 0, axis=1)), k
         partial += q < s_
     assert partial > 0, "no front with a partial Sigma support"
+    assert inert > 0, "no kept node uncoupled from S"
 
 
 

@@ -25,17 +25,26 @@ PEAK = {"fp64": 78.6, "mixed": 157.3}   # MI355X dense MFMA TFLOP/s (FP64, FP32)
 # HBM bytes per elimination-kernel launch of the 128x128 x 256-energy FP64
 # solve, from rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs (calibrated on a
 # plain copy; profiles/elim_kernels_c3_128x128_fp64.md).  Valid only for the
-# kernel source they were measured on.
-TRAFFIC_BYTES_PER_LAUNCH = 24902128919.5
-TRAFFIC_KERNEL_SHA = "4ac1cf2dcaeb8955"
-TRAFFIC_TILES = "44511100300001151500"
+# native sources (kernels, plan, C-ABI) they were measured on.
+TRAFFIC_BYTES_PER_LAUNCH = 20034839651.0
+TRAFFIC_KERNEL_SHA = "12e671ff7a3ec4e3"
+TRAFFIC_TILES = "44431106260011355500"
 TRAFFIC_FORM = (True, 2)   # (symmetric, energy groups) of the counter runs
 
 
-def measured_traffic(preset: str, precision: str, tiles: str, cmode: str, form: tuple):
+def native_source_sha() -> str:
+    """sha256 prefix over the native sources (csrc/*, sorted by name)."""
     import hashlib
-    src = os.path.join(ROOT, "paper_1104_0623_amd", "csrc", "kernels.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    d = os.path.join(ROOT, "paper_1104_0623_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        h.update(name.encode())
+        h.update(open(os.path.join(d, name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(preset: str, precision: str, tiles: str, cmode: str, form: tuple):
+    sha = native_source_sha()
     if (sha != TRAFFIC_KERNEL_SHA or tiles != TRAFFIC_TILES or preset != "c3_128x128" or precision != "fp64"
             or cmode != "4m" or form != TRAFFIC_FORM):
         return None

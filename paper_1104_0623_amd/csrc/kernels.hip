@@ -819,9 +819,10 @@ __global__ __launch_bounds__(NT, 3) void k_final(StageArgs a, OutArgs o) {
     if (tall_lu<RPT, NB, false>(L, FA, n, bp) && tid == 0) a.status[e] = 1;
     // G(:, perm[k]) = L(:, k): the L solve of the identity rows stores U_K^{-1}
     trsm_right_unit_lower(L, FA, G, n, bp, bp);
-    // T = R_K G^dagger   (gemm_sub returns 0 - R G^dagger)
-    const int sym = a.sym;
-    gemm_sub<NT>(bp, bp, bp,
+    // T = R_K G^dagger   (gemm_sub returns 0 - R G^dagger); R_K vanishes outside
+    // its first rs rows and columns, so T has rs rows and the sum runs over rs
+    const int sym = a.sym, rs = E.ssig;
+    gemm_sub<NT>(rs, bp, rs,
              [=](int r, int k) {
                if (sym && r < k) { const double2 v = Rin[(size_t)r * bp + k]; return make_double2(-v.x, v.y); }
                return Rin[(size_t)k * bp + r];
@@ -834,7 +835,7 @@ __global__ __launch_bounds__(NT, 3) void k_final(StageArgs a, OutArgs o) {
     const int lane = tid & 63, wave = tid >> 6;
     auto gless = [&](int i, int j) {
       double re = 0.0, im = 0.0;
-      for (int k = lane; k < bp; k += 64) {
+      for (int k = lane; k < rs; k += 64) {
         const double2 p = cmul(G[(size_t)k * bp + i], T[(size_t)j * bp + k]);
         re += p.x; im += p.y;
       }

@@ -44,7 +44,9 @@ int count_bonds(int Nx, int Ny, int stencil) {
 
 double elim_flops(const Elim& e, bool symmetric) {
   double s = e.s, b = e.b, q = e.ssig;
-  if (e.kind == K_FINAL) return 8.0 * 2.0 * s * s * s;
+  // final leaf block of size s: the inverse (s^3) and T = R_K G^dagger over the
+  // q rows and columns where R_K may be non-zero (q^2 s)
+  if (e.kind == K_FINAL) return 8.0 * (s * s * s + q * q * s);
   // complex multiply-adds: LU s^3/3 + s^2 b / 2, L s^2 b / 2, U = A(B,B) - L A(S,B)
   // s b^2.  Sigma_g is supported on the q eliminated nodes that carry Sigma< (and
   // the kept ones): W_q = Sigma(B,S_q) - L_q Sigma(S_q,S_q) costs b q^2 and
@@ -172,12 +174,15 @@ struct Builder {
   // an eliminated node carries Sigma< (the L Sigma(S,S) L^dagger terms fill
   // R), else the rows of the kept nodes that carry it (R = Sigma_g(B,B)).
   // With keep_out, the kept nodes coupled to S (a common source, a stencil
-  // bond, or one contact column) are moved ahead of the others, and the
-  // resulting kept order is stored there; otherwise `keep` is used as given.
+  // bond, or one contact column) are moved ahead of the others, then the
+  // uncoupled ones that carry Sigma<, and the resulting kept order is stored
+  // there; *rsup_out receives the number of kept nodes whose rows of R may be
+  // non-zero (coupled or carrying: R vanishes on the rest).  Otherwise `keep`
+  // is used as given.
   std::string emit(const std::vector<int>& list, const std::vector<int>& src,
                    const std::vector<int>& pos, const std::vector<int>& keep_in, Elim e,
                    const std::vector<char>* const sig_src[2], std::vector<char>* out_sig = nullptr,
-                   std::vector<int>* keep_out = nullptr) {
+                   std::vector<int>* keep_out = nullptr, int* rsup_out = nullptr) {
     std::vector<int> keep = keep_in;
     std::vector<int> keep_sorted = keep;
     std::sort(keep_sorted.begin(), keep_sorted.end());
@@ -225,6 +230,8 @@ struct Builder {
       std::iota(order.begin(), order.end(), 0);
       const auto mid = std::stable_partition(order.begin(), order.end(), [&](int q) { return coupled(in_list[q]); });
       e.bact = int(mid - order.begin());
+      const auto mid2 = std::stable_partition(mid, order.end(), [&](int q) { return !e.rzero && carries(in_list[q]); });
+      if (rsup_out) *rsup_out = e.rzero ? 0 : int(mid2 - order.begin());
       std::vector<int> k2, l2;
       for (int q : order) { k2.push_back(keep[q]); l2.push_back(in_list[q]); }
       keep.swap(k2); in_list.swap(l2);
@@ -338,6 +345,7 @@ struct Builder {
     for (int q = 0; q < nc; ++q) if (P.cl[q].leaf()) leaves.push_back(q);
     // pool slots for leaf blocks: sized for the larger variant, shared by both
     std::vector<int64_t> leaf1_off(leaves.size()), fin_off(leaves.size());
+    std::vector<int> rsup(leaves.size(), 0);
     std::vector<std::vector<std::array<int, 5>>> owned(leaves.size());
     for (size_t l = 0; l < leaves.size(); ++l) {
       const Cluster& c = P.cl[leaves[l]];
@@ -370,7 +378,7 @@ struct Builder {
         std::vector<int> keep = Cn;
         keep.insert(keep.end(), N.begin(), N.end());
         const std::vector<char>* sig_src[2] = {leaves[l] != 0 ? &c.dn_sig : nullptr, nullptr};
-        if (!(err = emit(list, src, pos, keep, e, sig_src, nullptr, &keeps[l])).empty()) return err;
+        if (!(err = emit(list, src, pos, keep, e, sig_src, nullptr, &keeps[l], &rsup[l])).empty()) return err;
       }
       P.stages.push_back({first, int(P.elims.size()) - first, PH_LEAF, v});
       first = int(P.elims.size());
@@ -378,6 +386,9 @@ struct Builder {
         const Elim& le = P.elims[P.stages.back().first + l];
         Elim e; e.kind = K_FINAL; e.phase = PH_FINAL; e.cluster = leaves[l]; e.level = le.level;
         e.s = le.b; e.b = le.b; e.n = 2 * le.b;
+        // R_K is supported on its first rsup rows and columns (the Sigma<-carrying
+        // prefix of the final block); bact = b as every node is coupled
+        e.ssig = rsup[l]; e.bact = le.b;
         e.src_off[0] = le.dst; e.src_ld[0] = le.b; e.dst = fin_off[l];
         e.map = int(P.map_node.size());
         for (int r = 0; r < 2 * le.b; ++r) {

@@ -127,7 +127,7 @@ def test_zero_sigma_fronts_are_flagged_exactly(Nx, Ny, stencil, leaf):
             kind, s_, q_, q0 = el[k][0], float(el[k][1]), float(el[k][14]), float(el[k][15])
             b_ = float(el[k][16]) if kind == 0 else float(el[k][2])
             if kind == 1:
-                ok += 16 * s_ ** 3
+                ok += 8 * (s_ ** 3 + q_ ** 2 * s_)
             elif el[k][13]:
                 ok += 8 * (s_ ** 3 / 3 + s_ ** 2 * b_ + s_ * b_ ** 2)
             else:
@@ -148,12 +148,26 @@ def test_sigma_support_prefix_is_exact(Nx, Ny, stencil, leaf):
     prob = inputs.make_problem(Nx, Ny, stencil, vmax=1.0, seed=11, energies=E, fL=0.7, fR=0.4)
     p = find.Plan(Nx, Ny, stencil, leaf=leaf)
     ex = p.export()
-    fronts = {}
+    fronts, rec = {}, {}
     Hm = dense.hamiltonian_matrix(Nx, Ny, prob["H"])
     for bonds in (False, True):
         execute(ex, Nx, Ny, stencil, Hm, E[0], prob["sigma"][0], prob["sigma_less"][0], want_bonds=bonds,
-                fronts=fronts)
+                fronts=fronts, record=rec)
     el = ex["elims"]
+    # final leaf blocks: R_K vanishes outside its first ssig rows and columns
+    # (the final stage follows its leaf-extraction stage, leaf by leaf)
+    st = [tuple(x) for x in ex["stages"]]
+    for i, (first, count, phase, var) in enumerate(st):
+        if phase != 3:
+            continue
+        lfirst = st[i - 1][0]
+        assert st[i - 1][2] == 2 and st[i - 1][1] == count
+        for q in range(count):
+            k, j = first + q, lfirst + q
+            R = rec[j][1]
+            rs = el[k][14]
+            assert el[k][2] == R.shape[0] and 0 <= rs <= R.shape[0]
+            assert np.all(R[rs:, :] == 0) and np.all(R[:, rs:] == 0), (k, rs)
     partial = inert = 0
     for k, (Ag, Sg) in fronts.items():
         kind, s_, b_, rz, q, bs, ba = (el[k][0], el[k][1], el[k][2], el[k][13], el[k][14], el[k][15],

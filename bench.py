@@ -6,7 +6,7 @@ step = one solve of the whole 256-energy batch (diag G + diag G<), inputs
 resident in HBM.  Prints one JSON line (see the repository's DESIGN notes for
 the roofline and CPU-baseline definitions).
 
-    python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--precision fp64|mixed]
+    python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--precision fp64|mixed|mixed-gless]
 """
 from __future__ import annotations
 
@@ -20,7 +20,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK = {"fp64": 78.6, "mixed": 157.3}   # MI355X dense MFMA TFLOP/s (FP64, FP32)
+# MI355X dense MFMA TFLOP/s: FP64, FP32 for the form whose Schur products are all
+# FP32, FP64 for the one that keeps U in FP64 (most of its flops)
+PEAK = {"fp64": 78.6, "mixed": 157.3, "mixed-gless": 78.6}
+PRECISION = {"fp64": 0, "mixed": 1, "mixed-gless": 2}   # find_precision values
 
 # HBM bytes per elimination-kernel launch of the 128x128 x 256-energy FP64
 # solve, from rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs (calibrated on a
@@ -86,7 +89,8 @@ def serve_bench(args) -> dict:
     from paper_1104_0623_amd.serve import GpuExecutor, Server, poisson_trace
     res = {}
     rates = [float(r) for r in args.rates.split(",")] if args.rates else [args.rate]
-    for prec_name, prec in (("fp64", find.PREC_FP64), ("mixed", find.PREC_MIXED)):
+    for prec_name in args.serve_precisions.split(","):
+        prec = PRECISION[prec_name]
         for rate in rates:
             trace = poisson_trace(args.serve_requests, rate=rate, seed=0)
             ex = GpuExecutor(n_slots=args.slots, precision=prec, plan_budget=16 << 30, cache_limit=96 << 30,
@@ -110,7 +114,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--precision", choices=["fp64", "mixed", "mixed-gless"], default="fp64")
     ap.add_argument("--preset", default="c3_128x128")
     ap.add_argument("--leaf", type=int, default=8, help="largest leaf-cluster side of the tree")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -119,6 +123,8 @@ def main() -> int:
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--rates", default="", help="comma-separated arrival rates for a sweep")
     ap.add_argument("--serve-requests", type=int, default=40)
+    ap.add_argument("--serve-precisions", default="fp64,mixed-gless",
+                    help="comma-separated forms served in turn (fp64, mixed, mixed-gless)")
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--no-graph", action="store_true",
                     help="launch each step eagerly instead of replaying one captured hipGraph")
@@ -171,7 +177,7 @@ def main() -> int:
     SL = torch.as_tensor(prob["sigma_less"], device=dev)
     dG = torch.empty((nE, Ny, Nx), dtype=torch.complex128, device=dev)
     dL = torch.empty_like(dG)
-    prec = find.PREC_MIXED if args.precision == "mixed" else find.PREC_FP64
+    prec = PRECISION[args.precision]
     cmode = find.CPLX_3M if args.complex_mode == "3m" else find.CPLX_4M
     plan = find.Plan(Nx, Ny, st, leaf=args.leaf, precision=prec, complex_mode=cmode, symmetric=not args.general,
                      streams=args.streams)
@@ -269,7 +275,7 @@ def main() -> int:
                      "launches": nl, "kernel_ms_per_step": kms / args.steps,
                      "algorithmic_flops_per_step": kflops / args.steps},
     }
-    if args.precision == "mixed":
+    if args.precision != "fp64":
         # error of this result against the FP64 form of the same solve, per energy
         ref = find.Plan(Nx, Ny, st, precision=find.PREC_FP64)
         rG = torch.empty_like(dG); rL = torch.empty_like(dL)

@@ -64,17 +64,22 @@ typedef enum {
   FIND_E_UNSUPPORTED = 5  /* shape beyond what the kernels support             */
 } find_status;
 
-typedef enum { FIND_PREC_FP64 = 0, FIND_PREC_MIXED = 1 } find_precision;
+typedef enum { FIND_PREC_FP64 = 0, FIND_PREC_MIXED = 1, FIND_PREC_MIXED_GLESS = 2 } find_precision;
 typedef enum { FIND_CPLX_4M = 0, FIND_CPLX_3M = 1 } find_complex_mode;
 
 /* Plan options; pass NULL for defaults.
  *   leaf          largest leaf-cluster side (default 8): the mesh is bisected
  *                 along its longer side (y on ties) until both sides <= leaf
  *                 (paper Sec. 2.1, the nested-dissection partition).
- *   precision     FIND_PREC_FP64 (default) or FIND_PREC_MIXED.  In the mixed
- *                 form the Schur-complement and Sigma products of eq.
- *                 (major-update) and eq. (gless-update-rule) run in FP32 on
- *                 MFMA (FP32 accumulation); the LU of A(S,S), the L solve,
+ *   precision     FIND_PREC_FP64 (default), FIND_PREC_MIXED or
+ *                 FIND_PREC_MIXED_GLESS.  In FIND_PREC_MIXED the
+ *                 Schur-complement and Sigma products of eq. (major-update)
+ *                 and eq. (gless-update-rule) run in FP32 on MFMA (FP32
+ *                 accumulation); in FIND_PREC_MIXED_GLESS only the Sigma
+ *                 products of eq. (gless-update-rule) do (the G< part: W and
+ *                 R), while U = A(B,B) - L A(S,B) stays FP64, so diag G is the
+ *                 FP64 result and diag G< carries the FP32 rounding of the
+ *                 Sigma products only.  In both, the LU of A(S,S), the L solve,
  *                 the final leaf blocks, every elimination of a cluster at
  *                 tree depth <= fp64_top_levels, and every elimination with
  *                 s >= 512 stay FP64.  Stored U/R blocks are FP64.
@@ -95,8 +100,12 @@ typedef enum { FIND_CPLX_4M = 0, FIND_CPLX_3M = 1 } find_complex_mode;
  *                 the paper) and every R anti-Hermitian, so only their lower
  *                 triangles are formed and the upper triangles are mirrored
  *                 (s b^2 fewer complex multiply-adds per elimination; the
- *                 flop model of find_plan_flops follows).  Inputs that break
- *                 the assertion give wrong results.  0 (default) = general.
+ *                 flop model of find_plan_flops follows).  In the mixed
+ *                 forms only U is halved: R is formed whole, because the FP32
+ *                 rounding of its products is not anti-Hermitian and
+ *                 mirroring one triangle amplifies it near resonances.
+ *                 Inputs that break the assertion give wrong results.
+ *                 0 (default) = general.
  *   streams       energy groups solved concurrently inside one pass (0 or 1
  *                 = one, on the caller's stream; 2..4 = that many groups, each
  *                 on a stream of the plan, forked from and joined back to the

@@ -117,6 +117,15 @@ find_status upload(T** dptr, const std::vector<T>& h, size_t& bytes) {
   return FIND_OK;
 }
 
+// Halved triangles of the symmetric form: bit 0 = U (complex symmetric), bit
+// 1 = R (anti-Hermitian).  The mixed forms form R whole: the FP32 rounding of
+// its products is not anti-Hermitian, and mirroring one triangle amplifies it
+// at energies near resonances of the device.
+int sym_bits(const find_plan_opts& o) {
+  if (!o.symmetric) return 0;
+  return o.precision == FIND_PREC_FP64 ? 3 : 1;
+}
+
 // Workspace (complex elements) of one Schur elimination: the tall block
 // [A(S,S); A(B,S)] (n x s), L (b x s) and W_q (b x ssig).
 long long elim_ws(const Elim& e) {
@@ -154,10 +163,12 @@ find_status ensure_device(find_plan_s* p, DevState** out) {
       // mixed form: FP32 products except the top-level eliminations, large
       // separators and the final leaf blocks, which stay FP64
       const int top = p->opts.fp64_top_levels == 0 ? 2 : p->opts.fp64_top_levels;
-      d.f32 = (p->opts.precision == FIND_PREC_MIXED && e.kind == K_SCHUR && e.level > top && e.s < 512) ? 1 : 0;
+      // bit 0: U product in FP32, bit 1: W and R (Sigma) products in FP32
+      const bool low = e.kind == K_SCHUR && e.level > top && e.s < 512;
+      d.f32 = !low ? 0 : p->opts.precision == FIND_PREC_MIXED ? 3 : p->opts.precision == FIND_PREC_MIXED_GLESS ? 2 : 0;
       maxn = std::max(maxn, e.n);
       ds_st.maxb = std::max(ds_st.maxb, e.b);
-      ds_st.flops_per_energy += elim_flops(e, p->opts.symmetric != 0);
+      ds_st.flops_per_energy += elim_flops(e, sym_bits(p->opts));
       const long long need = e.kind == K_FINAL ? 3LL * e.b * e.b  // [U; I] and T
                                                : elim_ws(e);          // tall block, L and W_q
       ds_st.ws_stride = std::max<long long>(ds_st.ws_stride, need);
@@ -272,7 +283,7 @@ find_status find_plan_create(int Nx, int Ny, int stencil, const find_plan_opts* 
   if (opts) o = *opts;
   if (o.leaf == 0) o.leaf = 8;
   if (o.leaf < 1) return fail(FIND_E_ARG, "find_plan_create: leaf must be >= 1");
-  if (o.precision != FIND_PREC_FP64 && o.precision != FIND_PREC_MIXED)
+  if (o.precision != FIND_PREC_FP64 && o.precision != FIND_PREC_MIXED && o.precision != FIND_PREC_MIXED_GLESS)
     return fail(FIND_E_ARG, "find_plan_create: unknown precision");
   if (o.max_energies < 0) return fail(FIND_E_ARG, "find_plan_create: max_energies must be >= 0");
   if (o.complex_mode != FIND_CPLX_4M && o.complex_mode != FIND_CPLX_3M)
@@ -365,7 +376,8 @@ find_status find_plan_export(find_plan plan, int32_t* elims, int32_t* maps, int3
 
 find_status find_plan_flops(find_plan plan, int want_bonds, double* flops_per_energy) {
   if (!plan || !flops_per_energy) return fail(FIND_E_ARG, "find_plan_flops: NULL argument");
-  *flops_per_energy = plan->P.flops[plan->opts.symmetric ? 1 : 0][want_bonds ? 1 : 0];
+  const int sb = sym_bits(plan->opts);
+  *flops_per_energy = plan->P.flops[sb == 0 ? 0 : sb == 3 ? 1 : 2][want_bonds ? 1 : 0];
   return FIND_OK;
 }
 
@@ -459,7 +471,7 @@ void pass_args(const find_plan_s* plan, const DevState* d, int variant, int e0, 
   a.ws = d->ws;   // (an energy group of a multi-stream pass offsets this)
   a.Nx = P.Nx; a.Ny = P.Ny; a.nst = P.stencil == 9 ? 5 : 3;
   a.status = d->status + e0;
-  a.sym = plan->opts.symmetric;
+  a.sym = sym_bits(plan->opts);
   OutArgs o{};
   o.leaves = d->d_leafout[variant];
   o.outnode = d->d_outnode; o.outbond = d->d_outbond; o.H = H;

@@ -135,7 +135,7 @@ struct Front {
   const double2* U1;
   int ld0, ld1;
   Orig o;
-  int sym;             // sources hold only the lower triangle of U (= U^T) and R (= -R^dagger)
+  int sym;             // sources hold only the lower triangle of U (= U^T) (bit 0) and of R (= -R^dagger) (bit 1)
 
   __device__ double2 a(int r, int c) const {
     const int spr = srcpos[r], spc = srcpos[c];
@@ -144,7 +144,7 @@ struct Front {
       const double2* U = sr ? U1 : U0;
       const int ld = sr ? ld1 : ld0;
       int pr = spr & 0xffffff, pc = spc & 0xffffff;
-      if (sym && pr < pc) { const int t = pr; pr = pc; pc = t; }
+      if ((sym & 1) && pr < pc) { const int t = pr; pr = pc; pc = t; }
       return U[(size_t)pc * ld + pr];
     }
     const int gr = node[r], gc = node[c];
@@ -157,7 +157,7 @@ struct Front {
       const int ld = sr ? ld1 : ld0;
       const double2* R = (sr ? U1 : U0) + (size_t)ld * ld;
       const int pr = spr & 0xffffff, pc = spc & 0xffffff;
-      if (sym && pr < pc) { const double2 v = R[(size_t)pr * ld + pc]; return make_double2(-v.x, v.y); }
+      if ((sym & 2) && pr < pc) { const double2 v = R[(size_t)pr * ld + pc]; return make_double2(-v.x, v.y); }
       return R[(size_t)pc * ld + pr];
     }
     const int gr = node[r], gc = node[c];
@@ -757,17 +757,17 @@ __global__ __launch_bounds__(NT, TC == kTileWg ? 2 : 3) void k_stage(StageArgs a
     // with a.sym, U is complex symmetric and R anti-Hermitian: their tiles
     // above the diagonal are not formed, and every reader of U and R takes
     // an upper entry from its mirror below the diagonal
-    const int tri = a.sym ? ba : 0;
-    auto products = [&](auto f32) {
-      constexpr bool F = decltype(f32)::value;
-      gemm_schur<NT, F, TC, CM == 1>(L, ba, ba, s, tri, lo_, bu, cu, su);
+    const int tri = (a.sym & 1) ? ba : 0, trir = (a.sym & 2) ? ba : 0;
+    auto products = [&](auto fu, auto fs) {
+      constexpr bool FU = decltype(fu)::value, FS = decltype(fs)::value;
+      gemm_schur<NT, FU, TC, CM == 1>(L, ba, ba, s, tri, lo_, bu, cu, su);
       if (E.rzero) {
         // Sigma< vanishes on this front: R = 0
         for_each_rc<NT>(b, b, [&](int r, int c) { Ro[(size_t)c * b + r] = zero2(); });
       } else {
-        if (q > 0) gemm_schur<NT, F, TC, CM == 1>(L, ba, q, q, 0, lo_, bw, cw, sw);
+        if (q > 0) gemm_schur<NT, FS, TC, CM == 1>(L, ba, q, q, 0, lo_, bw, cw, sw);
         __syncthreads();
-        gemm_schur<NT, F, TC, CM == 1>(L, ba, ba, q0 + q, tri, ar, br, cr, sr);
+        gemm_schur<NT, FS, TC, CM == 1>(L, ba, ba, q0 + q, trir, ar, br, cr, sr);
       }
     };
     // rows and columns of the kept nodes not coupled to S: U and R keep the
@@ -779,8 +779,9 @@ __global__ __launch_bounds__(NT, TC == kTileWg ? 2 : 3) void k_stage(StageArgs a
           if (!E.rzero) Ro[(size_t)c * b + r] = fr.s(s + r, s + c);
         }
       });
-    if (E.f32) products(std::true_type{});
-    else products(std::false_type{});
+    if (E.f32 == 3) products(std::true_type{}, std::true_type{});
+    else if (E.f32 == 2) products(std::false_type{}, std::true_type{});
+    else products(std::false_type{}, std::false_type{});
     __syncthreads();
   }
 }
@@ -812,7 +813,7 @@ __global__ __launch_bounds__(NT, 3) void k_final(StageArgs a, OutArgs o) {
     double2* G = pool + E.dst;                    // G(K,K), bp x bp
     for (int k = tid; k < bp; k += NT) L.perm[k] = k;
     for_each_rc<NT>(n, bp, [&](int r, int c) {
-      FA[(size_t)c * n + r] = r < bp ? Uin[a.sym && r < c ? (size_t)r * bp + c : (size_t)c * bp + r]
+      FA[(size_t)c * n + r] = r < bp ? Uin[(a.sym & 1) && r < c ? (size_t)r * bp + c : (size_t)c * bp + r]
                                      : make_double2(r - bp == c ? 1.0 : 0.0, 0.0);
     });
     __syncthreads();
@@ -821,10 +822,10 @@ __global__ __launch_bounds__(NT, 3) void k_final(StageArgs a, OutArgs o) {
     trsm_right_unit_lower(L, FA, G, n, bp, bp);
     // T = R_K G^dagger   (gemm_sub returns 0 - R G^dagger); R_K vanishes outside
     // its first rs rows and columns, so T has rs rows and the sum runs over rs
-    const int sym = a.sym, rs = E.ssig;
+    const int symr = a.sym & 2, rs = E.ssig;
     gemm_sub<NT>(rs, bp, rs,
              [=](int r, int k) {
-               if (sym && r < k) { const double2 v = Rin[(size_t)r * bp + k]; return make_double2(-v.x, v.y); }
+               if (symr && r < k) { const double2 v = Rin[(size_t)r * bp + k]; return make_double2(-v.x, v.y); }
                return Rin[(size_t)k * bp + r];
              },
              [=](int k, int c) { return conjd(G[(size_t)k * bp + c]); },

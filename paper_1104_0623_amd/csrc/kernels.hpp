@@ -13,7 +13,7 @@ struct ElimDev {
   long long dst;          // pool offset of the output U (b x b); R follows
   int map;                // first map entry
   int aux;                // final leaf block: index of its output record
-  int f32;                // 1: Schur/Sigma products in FP32 (mixed form)
+  int f32;                // bit 0: U product in FP32, bit 1: W and R (Sigma) products in FP32
   int rzero;              // 1: Sigma< vanishes on the front: R = 0, only U is formed
   int ssig;               // eliminated nodes carrying Sigma< (the first ssig of S)
   int bsig;               // 1: some kept node coupled to S carries Sigma<
@@ -38,7 +38,7 @@ struct StageArgs {
   long long ws_stride;
   int Nx, Ny, nst;
   int* status;            // per energy of this pass: 1 = zero pivot met
-  int sym;                // 1: A complex symmetric and Sigma< anti-Hermitian (form half of U and R)
+  int sym;                // bit 0: U complex symmetric (half formed), bit 1: R anti-Hermitian (half formed)
 };
 
 struct OutArgs {

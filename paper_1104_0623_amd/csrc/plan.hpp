@@ -66,12 +66,14 @@ struct Plan {
   int64_t pool_per_energy = 0;
   int max_n = 0, max_s = 0, max_b = 0;
   int n_bonds = 0;
-  double flops[2][2] = {{0, 0}, {0, 0}};  // per energy: [symmetric form][variant 0/1]
+  // per energy: [halved triangles: 0 none, 1 U and R, 2 U only][variant 0/1]
+  double flops[3][2] = {{0, 0}, {0, 0}, {0, 0}};
 };
 
 int count_bonds(int Nx, int Ny, int stencil);
 // Builds the plan; returns an empty string on success, else a message.
 std::string build_plan(int Nx, int Ny, int stencil, int leaf, Plan& P);
-double elim_flops(const Elim& e, bool symmetric = false);
+// sym: bit 0 = only half of U formed, bit 1 = only half of R formed
+double elim_flops(const Elim& e, int sym = 0);
 
 }  // namespace findmi

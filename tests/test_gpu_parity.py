@@ -276,6 +276,47 @@ def test_mixed_precision_c2_and_c3_sampled():
     assert np.median(eg) <= 1e-3 and np.median(el) <= 1e-3, (np.median(eg), np.median(el))
 
 
+GLESS_TOL = 1e-5
+
+
+@pytest.mark.parametrize("Nx,Ny,stencil,leaf", [(16, 16, 5, 2), (33, 20, 9, 4), (24, 40, 5, 4), (1, 11, 5, 2)])
+@pytest.mark.parametrize("sym", [False, True])
+def test_mixed_gless_small_meshes(Nx, Ny, stencil, leaf, sym):
+    """FIND_PREC_MIXED_GLESS: the Sigma products (W, R) in FP32, U in FP64.
+    G outputs are the FP64 form's bits; G< outputs carry only the FP32
+    rounding of the Sigma products."""
+    f = find()
+    E = np.array([0.41 + 1e-6j, -2.9 + 1e-6j, 1.3 + 1e-3j])
+    prob = inputs.make_problem(Nx, Ny, stencil, vmax=1.0, seed=Nx * 131 + Ny, energies=E, fL=1.0, fR=0.3)
+    ref = dense.dense_solve(Nx, Ny, stencil, prob["H"], E, prob["sigma"], prob["sigma_less"])
+    out = f.run_problem(f.Plan(Nx, Ny, stencil, leaf=leaf, precision=f.PREC_MIXED_GLESS, symmetric=sym), prob,
+                        want_bonds=True)
+    out64 = f.run_problem(f.Plan(Nx, Ny, stencil, leaf=leaf, symmetric=sym), prob, want_bonds=True)
+    assert np.array_equal(out["diag_G"], out64["diag_G"]) and np.array_equal(out["bond_G"], out64["bond_G"])
+    compare(out, ref, prob, tol=GLESS_TOL, label=f"mixed-gless {Nx}x{Ny}")
+    if Nx * Ny > 64:
+        assert not np.array_equal(out["diag_Gless"], out64["diag_Gless"])   # the FP32 path ran
+
+
+def test_mixed_gless_c2_and_c3_sampled():
+    """The G<-only mixed form meets the 1e-4 contract on the 64x64 and 128x128
+    workloads (per energy, against the RGF oracle)."""
+    f = find()
+    prob = inputs.make_preset("c2_64x64")
+    out = f.run_problem(f.Plan(64, 64, 5, precision=f.PREC_MIXED_GLESS, symmetric=True), prob, want_bonds=True)
+    ref = rgf.rgf_solve(64, 64, 5, prob["H"], prob["energies"], prob["sigma"], prob["sigma_less"])
+    compare(out, ref, prob, tol=GLESS_TOL, label="mixed-gless c2")
+    prob = inputs.make_preset("c3_128x128")
+    out = f.run_problem(f.Plan(128, 128, 5, precision=f.PREC_MIXED_GLESS, symmetric=True), prob, want_bonds=False)
+    sample = list(range(0, 256, 17))
+    ref = rgf.rgf_solve(128, 128, 5, prob["H"], prob["energies"][sample], prob["sigma"][sample],
+                        prob["sigma_less"][sample], bonds=False)
+    eg = [nrel(out["diag_G"][e], ref["diag_G"][q]) for q, e in enumerate(sample)]
+    el = [nrel(out["diag_Gless"][e], ref["diag_Gless"][q]) for q, e in enumerate(sample)]
+    print("mixed-gless c3 sampled: max diag G", max(eg), "max diag G<", max(el))
+    assert max(eg) <= TOL and max(el) <= 1e-4, (max(eg), max(el))
+
+
 def test_concurrent_energy_groups_match_one_stream():
     """Energy groups on the plan's own streams give the same bits as one stream
     (also with several passes and the bond outputs)."""

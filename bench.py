@@ -29,9 +29,9 @@ PRECISION = {"fp64": 0, "mixed": 1, "mixed-gless": 2}   # find_precision values
 # solve, from rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs (calibrated on a
 # plain copy; profiles/elim_kernels_c3_128x128_fp64.md).  Valid only for the
 # native sources (kernels, plan, C-ABI) they were measured on.
-TRAFFIC_BYTES_PER_LAUNCH = 20034839651.0
-TRAFFIC_KERNEL_SHA = "12e671ff7a3ec4e3"
-TRAFFIC_TILES = "44431106260011355500"
+TRAFFIC_BYTES_PER_LAUNCH = 20233951111.0
+TRAFFIC_KERNEL_SHA = "5fa12798077f5c2c"
+TRAFFIC_TILES = "44451106300111555500"
 TRAFFIC_FORM = (True, 2)   # (symmetric, energy groups) of the counter runs
 
 

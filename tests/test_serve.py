@@ -78,20 +78,24 @@ def test_small_budget_serialises_and_oversize_rejected():
 
 
 @pytest.mark.gpu
-def test_gpu_results_alone_equal_results_in_the_mix():
+@pytest.mark.parametrize("precision", [0, 2])
+def test_gpu_results_alone_equal_results_in_the_mix(precision):
+    """FP64 (0) and the G<-only mixed form (2, the serving comparison): every
+    result of a concurrent trace equals the same request solved alone."""
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_1104_0623_amd import find
     from paper_1104_0623_amd.serve import GpuExecutor, poisson_trace
     trace = poisson_trace(10, rate=500.0, seed=3, sizes=(16, 24, 40), max_energies=6, want_bonds=True)
-    ex = GpuExecutor(n_slots=4, precision=find.PREC_FP64, plan_budget=4 << 30, cache_limit=32 << 30)
+    ex = GpuExecutor(n_slots=4, precision=precision, plan_budget=4 << 30, cache_limit=32 << 30)
     srv = Server(ex, n_slots=4, hbm_budget=64 << 30)
     mix = {c.rid: c.outputs for c in srv.run(trace)}
     assert srv.max_concurrent >= 2
     for r in trace:
-        alone = find.run_problem(find.Plan(*r.key), dict(energies=r.energies, H=r.H, sigma=r.sigma,
-                                                         sigma_less=r.sigma_less), want_bonds=True)
+        alone = find.run_problem(find.Plan(*r.key, precision=precision),
+                                 dict(energies=r.energies, H=r.H, sigma=r.sigma, sigma_less=r.sigma_less),
+                                 want_bonds=True)
         for k in alone:
             assert np.array_equal(alone[k], mix[r.rid][k]), (r.rid, k)
     st = srv.stats()

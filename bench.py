@@ -29,9 +29,9 @@ PRECISION = {"fp64": 0, "mixed": 1, "mixed-gless": 2}   # find_precision values
 # solve, from rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs (calibrated on a
 # plain copy; profiles/elim_kernels_c3_128x128_fp64.md).  Valid only for the
 # native sources (kernels, plan, C-ABI) they were measured on.
-TRAFFIC_BYTES_PER_LAUNCH = 20233951111.0
-TRAFFIC_KERNEL_SHA = "5fa12798077f5c2c"
-TRAFFIC_TILES = "44451106300111555500"
+TRAFFIC_BYTES_PER_LAUNCH = 19622682098.9
+TRAFFIC_KERNEL_SHA = "d15c18d095911533"
+TRAFFIC_TILES = "44551106360111355500"
 TRAFFIC_FORM = (True, 2)   # (symmetric, energy groups) of the counter runs
 
 
@@ -52,6 +52,22 @@ def measured_traffic(preset: str, precision: str, tiles: str, cmode: str, form: 
             or cmode != "4m" or form != TRAFFIC_FORM):
         return None
     return TRAFFIC_BYTES_PER_LAUNCH
+
+
+def plain_find_flops(plan) -> float:
+    """Flops per energy of the plain dense-per-front FIND on the same tree
+    (diagonal outputs): 8 (s^3/3 + 2 s^2 b + 3 s b^2) per elimination and 16 b^3
+    per final leaf block, with no structural zero left out and nothing halved."""
+    ex = plan.export()
+    el = ex["elims"].astype(float)
+    total = 0.0
+    for first, count, phase, var in ex["stages"]:
+        if var not in (-1, 0):
+            continue
+        for k in range(first, first + count):
+            s_, b_ = el[k][1], el[k][2]
+            total += 16 * b_ ** 3 if el[k][0] == 1 else 8 * (s_ ** 3 / 3 + 2 * s_ * s_ * b_ + 3 * s_ * b_ * b_)
+    return total
 
 
 def cpu_baseline(prob: dict, budget_s: float = 12.0) -> dict:
@@ -181,6 +197,7 @@ def main() -> int:
     cmode = find.CPLX_3M if args.complex_mode == "3m" else find.CPLX_4M
     plan = find.Plan(Nx, Ny, st, leaf=args.leaf, precision=prec, complex_mode=cmode, symmetric=not args.general,
                      streams=args.streams)
+    plain_flops = plain_find_flops(plan)
     stream = torch.cuda.Stream()          # non-default stream (graph capture needs one)
     torch.cuda.set_stream(stream)
     tune_s = 0.0
@@ -273,7 +290,12 @@ def main() -> int:
                      "kernel": "k_stage + k_final (elimination kernels, all stage launches)",
                      "timing": "HIP events per stage launch" if args.no_graph else "HIP events around each graph replay",
                      "launches": nl, "kernel_ms_per_step": kms / args.steps,
-                     "algorithmic_flops_per_step": kflops / args.steps},
+                     "algorithmic_flops_per_step": kflops / args.steps,
+                     # context: the plain dense-per-front FIND's work on the same tree per
+                     # step, over the same kernel time (the rate this run delivers in
+                     # plain-FIND work; achieved/frac above are on the form's own count)
+                     "plain_find_flops_per_step": plain_flops * nE,
+                     "plain_find_equivalent_TFLOPs": plain_flops * nE * args.steps / (kms * 1e9)},
     }
     if args.precision != "fp64":
         # error of this result against the FP64 form of the same solve, per energy

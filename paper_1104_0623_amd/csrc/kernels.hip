@@ -23,10 +23,16 @@
 //      and R = Sigma(B,B) - [L_q | W_q] [Sigma(S_q,B) ; L_q^dagger], with
 //      L_q = L(:,S_q) (the Sigma(S_q,B) half is skipped when no kept node
 //      carries Sigma<).
+// Kept nodes that share no source, stencil bond or contact column with S
+// (placed last in B by the plan; leaf extraction only) have zero rows and
+// columns of A_g(B,S) and Sigma_g(B,S): steps 1-5 run over the first bact
+// kept nodes, and U and R keep A_g(B,B), Sigma_g(B,B) for the others.
 // The row permutation P is never applied to the front: the LU reads row
 // perm[k] for the k-th pivot, and the L solve stores column k at perm[k].
 // Complex products run on v_mfma_f64_16x16x4_f64 as four real products
-// (re*re - im*im, re*im + im*re).
+// (re*re - im*im, re*im + im*re); in the mixed forms the U product (bit 0 of
+// ElimDev::f32) and the Sigma products (bit 1) may run on
+// v_mfma_f32_16x16x4_f32 instead.
 #include "kernels.hpp"
 
 #include <climits>

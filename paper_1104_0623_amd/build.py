@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfind.so")
 # (source, extra flags): kernels.hip is compiled once per kernel family
-SOURCES = [("plan.cpp", []), ("capi.hip", [])] + [("kernels.hip", [f"-DFIND_TU={k}"]) for k in (1, 2, 3, 4, 5, 6)]
+SOURCES = [("plan.cpp", []), ("capi.hip", [])] + [("kernels.hip", [f"-DFIND_TU={k}"]) for k in (1, 2, 3, 4, 5, 6, 7)]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -175,8 +175,8 @@ struct Front {
 // order inside a column, without integer division.
 template <int NT, class F>
 __device__ __forceinline__ void for_each_rc(int nr, int nc, F&& f) {
-  constexpr int LNT = NT == 64 ? 6 : NT == 128 ? 7 : 8;
-  static_assert((1 << LNT) == NT, "workgroup of 64, 128 or 256 threads");
+  constexpr int LNT = NT == 64 ? 6 : NT == 128 ? 7 : NT == 256 ? 8 : 9;
+  static_assert((1 << LNT) == NT, "workgroup of 64, 128, 256 or 512 threads");
   const int lg = nr <= 1 ? 0 : 32 - __clz(nr - 1);
   const int lgr = lg < LNT ? lg : LNT;
   const int rmask = (1 << lgr) - 1, cstep = NT >> lgr;
@@ -707,7 +707,7 @@ __device__ __forceinline__ void trsm_right_unit_lower(LDS& L, double2* FA, doubl
 }
 
 template <int RPT, int TC, int CM, int NT, int MAXN>
-__global__ __launch_bounds__(NT, TC == kTileWg ? 2 : 3) void k_stage(StageArgs a) {
+__global__ __launch_bounds__(NT, (TC == kTileWg || NT == 512) ? 2 : 3) void k_stage(StageArgs a) {
   constexpr int NB = 16 / RPT;  // panel columns held in registers
   __shared__ LdsT<NT, MAXN> L;
   const int tid = threadIdx.x;
@@ -876,7 +876,7 @@ __global__ __launch_bounds__(NT, 3) void k_final(StageArgs a, OutArgs o) {
 }
 
 #ifndef FIND_TU
-#error "kernels.hip is compiled once per kernel family: -DFIND_TU=1 .. 6"
+#error "kernels.hip is compiled once per kernel family: -DFIND_TU=1 .. 7"
 #endif
 // Launchers.  The source is compiled once per kernel family (FIND_TU = 1:
 // k_stage with 1 panel row per thread, 2: with 2, 3: with 4 and 8, 4: k_final,
@@ -912,6 +912,19 @@ hipError_t launch_stage_w(const StageArgs& a, int rpt, int cm, int grid, hipStre
   }
   FIND_LAUNCH_W(1, 0) FIND_LAUNCH_W(2, 0) FIND_LAUNCH_W(1, 1) FIND_LAUNCH_W(2, 1)
 #undef FIND_LAUNCH_W
+  return hipErrorInvalidValue;
+}
+#endif
+#if FIND_TU == 7
+// eight waves per front (one workgroup per CU, 256 VGPRs per lane)
+hipError_t launch_stage_w8(const StageArgs& a, int rpt, int cm, int grid, hipStream_t st) {
+#define FIND_LAUNCH_W8(R, C)                                                                   \
+  if (rpt == R && cm == C) {                                                                  \
+    hipLaunchKernelGGL((k_stage<R, 0, C, kEightWaveThreads, kEightWaveThreads * R>), dim3(grid), dim3(kEightWaveThreads), 0, st, a); \
+    return hipGetLastError();                                                                 \
+  }
+  FIND_LAUNCH_W8(1, 0) FIND_LAUNCH_W8(2, 0) FIND_LAUNCH_W8(4, 0) FIND_LAUNCH_W8(1, 1) FIND_LAUNCH_W8(2, 1) FIND_LAUNCH_W8(4, 1)
+#undef FIND_LAUNCH_W8
   return hipErrorInvalidValue;
 }
 #endif

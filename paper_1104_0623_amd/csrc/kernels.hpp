@@ -66,11 +66,14 @@ constexpr int kThreads = 256;
 // one 128-thread workgroup per front (fronts of at most kTwoWaveMaxFront
 // nodes), or kTileWg: 64x64 workgroup tiles whose operands the four waves
 // share through LDS (Schur products and LU trailing updates; fronts of at
-// most 512 nodes).  cm: 0 = 4M, 1 = 3M complex products.
-constexpr int kTileConfigs = 7;
+// most 512 nodes), or kTileEight: one 512-thread workgroup per front and per
+// CU, for stages with few, large fronts.  cm: 0 = 4M, 1 = 3M complex products.
+constexpr int kTileConfigs = 8;
 constexpr int kTileWave = 4;       // one wave (64 threads) per front
 constexpr int kTileTwoWave = 5;    // two waves (128 threads) per front
 constexpr int kTileWg = 6;         // 64x64 workgroup tiles staged through LDS
+constexpr int kTileEight = 7;      // eight waves (512 threads) per front, one workgroup per CU
+constexpr int kEightWaveThreads = 512;
 constexpr int kWaveMaxFront = 128;
 constexpr int kTwoWaveMaxFront = 256;
 // workgroups resident where one 256-thread workgroup is, for a configuration
@@ -79,6 +82,7 @@ inline int groups_per_slot(int tc) { return tc == kTileWave ? 4 : tc == kTileTwo
 // 256-thread slots (three per CU); the workgroup-tile form is compiled for
 // two workgroups per CU
 inline long long stage_grid_groups(long long slots, int tc) {
+  if (tc == kTileEight) return slots / 3;   // one eight-wave workgroup per CU
   return tc == kTileWg ? slots * 2 / 3 : slots * groups_per_slot(tc);
 }
 #define FIND_CAT_(a, b) a##b
@@ -88,20 +92,24 @@ hipError_t launch_stage_r2(const StageArgs& a, int tc, int cm, int grid, hipStre
 hipError_t launch_stage_r48(const StageArgs& a, int rpt, int tc, int cm, int grid, hipStream_t st);
 hipError_t launch_stage_w(const StageArgs& a, int rpt, int cm, int grid, hipStream_t st);
 hipError_t launch_stage_w2(const StageArgs& a, int rpt, int cm, int grid, hipStream_t st);
+hipError_t launch_stage_w8(const StageArgs& a, int rpt, int cm, int grid, hipStream_t st);
 hipError_t launch_final(const StageArgs& a, const OutArgs& o, int rpt, int grid, hipStream_t st);
 hipError_t launch_final_w(const StageArgs& a, const OutArgs& o, int rpt, int grid, hipStream_t st);
 hipError_t launch_final_w2(const StageArgs& a, const OutArgs& o, int rpt, int grid, hipStream_t st);
 // panel rows per thread of the one- and two-wave forms
 inline int wave_rpt(int n) { return n <= 64 ? 1 : 2; }
 inline int wave2_rpt(int n) { return n <= 128 ? 1 : 2; }
+inline int wave8_rpt(int n) { return n <= 512 ? 1 : n <= 1024 ? 2 : 4; }
 // bit mask of the tile configurations a stage with fronts of at most maxn nodes has
 inline int stage_tile_mask(int maxn, bool final_stage) {
   int m = final_stage ? 1 : (panel_rpt(maxn) <= 2 ? (0xf | 1 << kTileWg) : 1);
+  if (!final_stage) m |= 1 << kTileEight;
   if (maxn <= kWaveMaxFront) m |= 1 << kTileWave;
   if (maxn <= kTwoWaveMaxFront) m |= 1 << kTileTwoWave;
   return m;
 }
 inline hipError_t launch_stage(const StageArgs& a, int maxn, int tc, int cm, int grid, hipStream_t st) {
+  if (tc == kTileEight) return launch_stage_w8(a, wave8_rpt(maxn), cm, grid, st);
   if (tc == kTileWave) return maxn <= kWaveMaxFront ? launch_stage_w(a, wave_rpt(maxn), cm, grid, st) : hipErrorInvalidValue;
   if (tc == kTileTwoWave)
     return maxn <= kTwoWaveMaxFront ? launch_stage_w2(a, wave2_rpt(maxn), cm, grid, st) : hipErrorInvalidValue;

@@ -136,7 +136,7 @@ def test_tile_configurations_give_bitwise_equal_results():
     opts = plan.tile_options()
     assert any(4 in o for o in opts)     # the small-front stages have the one-wave form
     assert any(6 in o for o in opts)     # and the workgroup tile
-    for tc in (1, 2, 3, 4, 5, 6):
+    for tc in (1, 2, 3, 4, 5, 6, 7):
         plan.set_tiles([tc if tc in o else 0 for o in opts])
         out = f.run_problem(plan, prob, want_bonds=True)
         for k in base:

@@ -68,7 +68,7 @@ def test_tile_and_complex_mode_options():
         # workgroup tile; the final leaf blocks only the default; fronts <= 128
         # also the one-wave form, fronts <= 256 the two-wave form
         want = (([0] if final else [0, 1, 2, 3]) + ([4] if maxn <= 128 else []) + ([5] if maxn <= 256 else [])
-                + ([6] if not final and maxn <= 512 else []))
+                + ([6] if not final and maxn <= 512 else []) + ([] if final else [7]))
         assert o == want, (st, maxn, o)
     pick = [o[-1] for o in opts]
     plan.set_tiles(pick)

@@ -7,6 +7,11 @@ nearest neighbours together with the bond current J_{i->j} = 2 Re(H_ij G<_ji)
 (Sec. 3.2, current density; the formula for J is the standard NEGF bond
 current, with rho = -i G< per unit energy / 2pi).
 
+A diagonal scattering self-energy may be added on every node (the paper's
+problem statement, Sec. 1, takes the scattering self-energy of G< as
+typically diagonal): Sigma_d (retarded, subtracted from A) and Sigma<_d
+(added to Sigma<), both [nE][Ny][Nx].
+
 Complexity O(n^3) per energy with n = Nx*Ny; use for n <= ~4096.
 """
 from __future__ import annotations
@@ -65,8 +70,10 @@ def dense_A(Nx: int, Ny: int, H: np.ndarray, E: complex, sigma_e: np.ndarray) ->
 
 
 def dense_solve(Nx: int, Ny: int, stencil: int, H: np.ndarray, energies, sigma: np.ndarray,
-                sigma_less: np.ndarray, bonds: bool = True, keep_G: bool = False) -> dict:
-    """Per energy: G = inv(A); G< = G Sigma< G^dagger.
+                sigma_less: np.ndarray, bonds: bool = True, keep_G: bool = False,
+                sigma_d: np.ndarray | None = None, sigma_less_d: np.ndarray | None = None) -> dict:
+    """Per energy: G = inv(A); G< = G Sigma< G^dagger (with the diagonal
+    scattering terms sigma_d, sigma_less_d when given).
 
     Returns diag_G, diag_Gless ([nE][Ny][Nx] complex) and, if ``bonds``,
     bond_G = G_ij, bond_Gless = G<_ij and bond_J = 2 Re(H_ij G<_ji) for every
@@ -90,8 +97,12 @@ def dense_solve(Nx: int, Ny: int, stencil: int, H: np.ndarray, energies, sigma: 
         out["Gless"] = np.empty((nE, n, n), np.complex128)
     for e in range(nE):
         A = energies[e] * np.eye(n) - Hm - embed_contacts(Nx, Ny, sigma[e])
-        G = np.linalg.inv(A)
         Sl = embed_contacts(Nx, Ny, sigma_less[e])
+        if sigma_d is not None:
+            A -= np.diag(sigma_d[e].reshape(n))
+        if sigma_less_d is not None:
+            Sl += np.diag(sigma_less_d[e].reshape(n))
+        G = np.linalg.inv(A)
         Gl = G @ Sl @ G.conj().T
         out["diag_G"][e] = np.diag(G).reshape(Ny, Nx)
         out["diag_Gless"][e] = np.diag(Gl).reshape(Ny, Nx)

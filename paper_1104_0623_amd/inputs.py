@@ -119,6 +119,19 @@ def lesser_self_energies(sigma: np.ndarray, fL: float, fR: float) -> np.ndarray:
     return out
 
 
+def scattering_self_energies(Nx: int, Ny: int, nE: int, gamma: float = 0.05, f: float = 0.5,
+                             seed: int = 0) -> tuple[np.ndarray, np.ndarray]:
+    """Diagonal scattering self-energies on every node (Buttiker-probe-like
+    dephasing): Sigma_d = -i gamma_i / 2 with gamma_i ~ U[gamma/2, 3 gamma/2]
+    (seeded, linear-index order, the same for every energy) and
+    Sigma<_d = -f (Sigma_d - Sigma_d^*) = i f gamma_i.  Arrays [nE][Ny][Nx]."""
+    rng = np.random.default_rng(seed)
+    g = rng.uniform(0.5 * gamma, 1.5 * gamma, size=Nx * Ny).reshape(Ny, Nx)
+    sd = np.broadcast_to(-0.5j * g, (nE, Ny, Nx)).astype(np.complex128)
+    sl = -f * (sd - sd.conj())
+    return sd, np.ascontiguousarray(sl)
+
+
 def bond_counts(Nx: int, Ny: int, stencil: int) -> list[int]:
     n = [max(Nx - 1, 0) * Ny, Nx * max(Ny - 1, 0)]
     if stencil == 9:

@@ -160,3 +160,34 @@ def test_dense_matches_golden_fixture(name):
     assert rel(d["diag_Gless"][0].ravel(), cz(rec["diag_Gless"])) < 1e-12
     assert rel(d["bond_G"][0], cz(rec["bond_G"])) < 1e-12
     assert rel(d["bond_Gless"][0], cz(rec["bond_Gless"])) < 1e-12
+
+
+def test_scattering_self_energy_shift_and_identity():
+    """Diagonal scattering self-energies (the paper's typical diagonal Sigma):
+    a uniform Sigma_d = c is the energy shift E -> E - c with the contact
+    self-energies held fixed, and with one occupation f for contacts and
+    probes the eta-corrected identity -f (G - G^dagger) = G Sigma< G^dagger +
+    2 i eta f G G^dagger holds (A^dagger - A = Sigma - Sigma^dagger - 2 i eta I
+    with the probes included in Sigma)."""
+    Nx, Ny, f, eta = 5, 7, 0.4, 1e-3
+    E = np.array([0.3 + 1j * eta, -1.7 + 1j * eta])
+    p = inputs.make_problem(Nx, Ny, 9, vmax=0.7, seed=6, energies=E, fL=f, fR=f)
+    c = 0.013 - 0.021j
+    sd = np.full((E.size, Ny, Nx), c, np.complex128)
+    zero = np.zeros_like(sd)
+    a = dense.dense_solve(Nx, Ny, 9, p["H"], E, p["sigma"], p["sigma_less"], sigma_d=sd, sigma_less_d=zero)
+    b = dense.dense_solve(Nx, Ny, 9, p["H"], E - c, p["sigma"], p["sigma_less"])
+    for k in ("diag_G", "diag_Gless", "bond_G", "bond_Gless"):
+        assert rel(a[k], b[k]) < 1e-12, k
+    sd, sl = inputs.scattering_self_energies(Nx, Ny, E.size, gamma=0.08, f=f, seed=2)
+    d = dense.dense_solve(Nx, Ny, 9, p["H"], E, p["sigma"], p["sigma_less"], keep_G=True,
+                          sigma_d=sd, sigma_less_d=sl)
+    for e in range(E.size):
+        G, Gl = d["G"][e], d["Gless"][e]
+        assert rel(-f * (G - G.conj().T), Gl + 2j * eta * f * (G @ G.conj().T)) < 1e-11
+        assert rel(G, G.T) < 1e-12 and rel(Gl, -Gl.conj().T) < 1e-12
+    # a probe occupation different from the contacts' breaks the identity
+    d2 = dense.dense_solve(Nx, Ny, 9, p["H"], E, p["sigma"], p["sigma_less"], keep_G=True,
+                           sigma_d=sd, sigma_less_d=sl * 1.5)
+    G, Gl = d2["G"][0], d2["Gless"][0]
+    assert rel(-f * (G - G.conj().T), Gl + 2j * eta * f * (G @ G.conj().T)) > 1e-3

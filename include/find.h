@@ -111,7 +111,14 @@ typedef enum { FIND_CPLX_4M = 0, FIND_CPLX_3M = 1 } find_complex_mode;
  *                 on a stream of the plan, forked from and joined back to the
  *                 caller's stream with events, each with its own workspace),
  *                 so that one group's small late stages overlap another's.
- *                 Results do not depend on it. */
+ *                 Results do not depend on it.
+ *   scattering    1: the solves add diagonal scattering self-energies on
+ *                 every node (the paper's problem statement, Sec. 1, takes the
+ *                 scattering self-energy as typically diagonal): Sigma_d is
+ *                 subtracted from the diagonal of A and Sigma<_d added to the
+ *                 diagonal of Sigma<, both passed to find_solve_scattering.  Every
+ *                 node then carries Sigma<, so no front skips its W and R.
+ *                 0 (default): contacts only, find_solve. */
 typedef struct {
   int leaf;
   int precision;
@@ -121,7 +128,8 @@ typedef struct {
   int complex_mode;
   int symmetric;
   int streams;
-  int reserved[5];
+  int scattering;
+  int reserved[4];
 } find_plan_opts;
 
 /* Build the cluster tree, boundary sets, gather maps and level schedule for
@@ -164,6 +172,21 @@ find_status find_solve(find_plan plan, int nE, const double* energies, const dou
                        const double* sigma, const double* sigma_less, double* diag_G,
                        double* diag_Gless, double* bond_G, double* bond_Gless, double* bond_J,
                        void* hip_stream);
+
+/* find_solve for a plan created with opts.scattering = 1 (the diagonal
+ * scattering self-energies of the introduction, e.g. electron-phonon):
+ * A = E I - H - Sigma_L - Sigma_R - diag(Sigma_d) and Sigma< = Sigma<_L +
+ * Sigma<_R + diag(Sigma<_d), with sigma_d and sigma_less_d complex
+ * [nE][Ny][Nx] device arrays (node (x, y) at [e][y][x], like diag_G):
+ * Sigma_d retarded (Im <= 0), Sigma<_d anti-Hermitian, i.e. purely
+ * imaginary, for the symmetric form.  Both are read once per solve, before
+ * the first elimination, on `hip_stream`.  Other arguments and errors as
+ * find_solve; FIND_E_ARG also if the plan is not a scattering plan or
+ * sigma_d or sigma_less_d is NULL (find_solve rejects scattering plans). */
+find_status find_solve_scattering(find_plan plan, int nE, const double* energies, const double* H,
+                                  const double* sigma, const double* sigma_less, const double* sigma_d,
+                                  const double* sigma_less_d, double* diag_G, double* diag_Gless,
+                                  double* bond_G, double* bond_Gless, double* bond_J, void* hip_stream);
 
 /* Wait for `hip_stream`, then report FIND_E_SINGULAR if the last solve on
  * this plan met an exactly-zero pivot (the energy index is in

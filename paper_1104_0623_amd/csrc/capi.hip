@@ -77,6 +77,35 @@ __global__ void k_fill_int(int* p, int n, int v) {
   if (i < n) p[i] = v;
 }
 
+// Node diagonal of the pass's energies into the pool: D[e][0][i] = E_e - H_ii
+// - Sigma_d[e][i] (no Sigma_d without scattering) and D[e][1][i] =
+// Sigma<_d[e][i] (scattering only); read by the elimination kernels' gathers.
+__global__ void k_onsite(StageArgs a) {
+  const long long nn = (long long)a.Nx * a.Ny;
+  const long long total = nn * a.nE;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
+       t += (long long)gridDim.x * blockDim.x) {
+    const int e = int(t / nn);
+    const long long i = t - e * nn;
+    double2* D = a.pool + (size_t)e * a.pool_stride + a.onsite_off;
+    const double2 E = a.energies[e];
+    double2 v = make_double2(E.x - a.H[i], E.y);
+    if (a.sscat) {
+      const double2 sd = a.sscat[e * nn + i];
+      v.x -= sd.x; v.y -= sd.y;
+      D[nn + i] = a.slscat[e * nn + i];
+    }
+    D[i] = v;
+  }
+}
+
+hipError_t launch_onsite(const StageArgs& a, hipStream_t st) {
+  const long long total = (long long)a.Nx * a.Ny * a.nE;
+  const int grid = int(std::min<long long>((total + 255) / 256, 4096));
+  hipLaunchKernelGGL(k_onsite, dim3(grid), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 struct find_plan_s {
@@ -290,13 +319,14 @@ find_status find_plan_create(int Nx, int Ny, int stencil, const find_plan_opts* 
     return fail(FIND_E_ARG, "find_plan_create: unknown complex_mode");
   if (o.symmetric != 0 && o.symmetric != 1) return fail(FIND_E_ARG, "find_plan_create: symmetric must be 0 or 1");
   if (o.streams < 0 || o.streams > 4) return fail(FIND_E_ARG, "find_plan_create: streams must be 0..4");
+  if (o.scattering != 0 && o.scattering != 1) return fail(FIND_E_ARG, "find_plan_create: scattering must be 0 or 1");
   if ((long long)Nx * Ny > (1LL << 24)) return fail(FIND_E_UNSUPPORTED, "find_plan_create: mesh larger than 2^24 nodes");
   find_plan_s* p = new (std::nothrow) find_plan_s();
   if (!p) return fail(FIND_E_NOMEM, "find_plan_create: host allocation failed");
   p->opts = o;
   std::string err;
   try {
-    err = build_plan(Nx, Ny, stencil, o.leaf, p->P);
+    err = build_plan(Nx, Ny, stencil, o.leaf, p->P, o.scattering != 0);
   } catch (const std::exception& ex) {
     err = std::string("find_plan_create: ") + ex.what();
   }
@@ -456,7 +486,7 @@ find_status prepare(find_plan_s* plan, int nE, hipStream_t st, DevState** dout, 
 void pass_args(const find_plan_s* plan, const DevState* d, int variant, int e0, int ne, const double* energies,
                const double* H, const double* sigma, const double* sigma_less, double* diag_G,
                double* diag_Gless, double* bond_G, double* bond_Gless, double* bond_J, StageArgs* pa,
-               OutArgs* po) {
+               OutArgs* po, const double* sigma_d = nullptr, const double* sigma_less_d = nullptr) {
   const Plan& P = plan->P;
   const size_t nx2 = size_t(P.Nx) * P.Nx;
   const size_t nnodes = size_t(P.Nx) * P.Ny;
@@ -467,6 +497,9 @@ void pass_args(const find_plan_s* plan, const DevState* d, int variant, int e0, 
   a.H = H;
   a.sigma = reinterpret_cast<const double2*>(sigma) + size_t(e0) * 2 * nx2;
   a.sless = reinterpret_cast<const double2*>(sigma_less) + size_t(e0) * 2 * nx2;
+  a.sscat = sigma_d ? reinterpret_cast<const double2*>(sigma_d) + size_t(e0) * nnodes : nullptr;
+  a.slscat = sigma_less_d ? reinterpret_cast<const double2*>(sigma_less_d) + size_t(e0) * nnodes : nullptr;
+  a.onsite_off = P.onsite_off;
   a.pool = d->pool; a.pool_stride = P.pool_per_energy;
   a.ws = d->ws;   // (an energy group of a multi-stream pass offsets this)
   a.Nx = P.Nx; a.Ny = P.Ny; a.nst = P.stencil == 9 ? 5 : 3;
@@ -498,17 +531,12 @@ hipError_t launch_stage_k(const find_plan_s* plan, const DevState* d, int k, Sta
   return launch_stage(a, s2.maxn, tc, plan->opts.complex_mode, grid, st);
 }
 
-}  // namespace
-
-extern "C" {
-
-find_status find_solve(find_plan plan, int nE, const double* energies, const double* H, const double* sigma,
-                       const double* sigma_less, double* diag_G, double* diag_Gless, double* bond_G,
-                       double* bond_Gless, double* bond_J, void* hip_stream) {
-  if (!plan) return fail(FIND_E_ARG, "find_solve: NULL plan");
-  if (nE < 1) return fail(FIND_E_ARG, "find_solve: nE must be >= 1");
-  if (!energies || !H || !sigma || !sigma_less || !diag_G || !diag_Gless)
-    return fail(FIND_E_ARG, "find_solve: NULL input or diagonal output pointer");
+// The solve of find_solve and find_solve_scattering (sigma_d and sigma_less_d
+// NULL for the former); arguments checked by the callers.
+find_status solve_impl(find_plan plan, int nE, const double* energies, const double* H, const double* sigma,
+                       const double* sigma_less, const double* sigma_d, const double* sigma_less_d,
+                       double* diag_G, double* diag_Gless,
+                       double* bond_G, double* bond_Gless, double* bond_J, void* hip_stream) {
   std::lock_guard<std::mutex> lk(plan->mu);
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   DevState* d = nullptr;
@@ -551,9 +579,13 @@ find_status find_solve(find_plan plan, int nE, const double* energies, const dou
       StageArgs a;
       OutArgs o;
       pass_args(plan, d, variant, g0, gn, energies, H, sigma, sigma_less, diag_G, diag_Gless, bond_G, bond_Gless,
-                bond_J, &a, &o);
+                bond_J, &a, &o, sigma_d, sigma_less_d);
       a.ws = d->ws + size_t(g) * lws;
       a.pool = d->pool + size_t(g0 - e0) * size_t(plan->P.pool_per_energy);   // kernels index energies from 0
+      {
+        const hipError_t he = launch_onsite(a, sg);
+        if (he != hipSuccess) return fail(FIND_E_DEVICE, std::string("onsite launch: ") + hipGetErrorString(he));
+      }
       for (size_t k = 0; k < d->stages.size(); ++k) {
         const DevStage& s2 = d->stages[k];
         if (s2.variant >= 0 && s2.variant != variant) continue;
@@ -591,10 +623,43 @@ find_status find_solve(find_plan plan, int nE, const double* energies, const dou
   return FIND_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+find_status find_solve(find_plan plan, int nE, const double* energies, const double* H, const double* sigma,
+                       const double* sigma_less, double* diag_G, double* diag_Gless, double* bond_G,
+                       double* bond_Gless, double* bond_J, void* hip_stream) {
+  if (!plan) return fail(FIND_E_ARG, "find_solve: NULL plan");
+  if (nE < 1) return fail(FIND_E_ARG, "find_solve: nE must be >= 1");
+  if (!energies || !H || !sigma || !sigma_less || !diag_G || !diag_Gless)
+    return fail(FIND_E_ARG, "find_solve: NULL input or diagonal output pointer");
+  if (plan->opts.scattering)
+    return fail(FIND_E_ARG, "find_solve: the plan expects scattering self-energies (find_solve_scattering)");
+  return solve_impl(plan, nE, energies, H, sigma, sigma_less, nullptr, nullptr, diag_G, diag_Gless, bond_G,
+                    bond_Gless, bond_J, hip_stream);
+}
+
+find_status find_solve_scattering(find_plan plan, int nE, const double* energies, const double* H,
+                                  const double* sigma, const double* sigma_less, const double* sigma_d,
+                                  const double* sigma_less_d, double* diag_G, double* diag_Gless,
+                                  double* bond_G, double* bond_Gless, double* bond_J, void* hip_stream) {
+  if (!plan) return fail(FIND_E_ARG, "find_solve_scattering: NULL plan");
+  if (nE < 1) return fail(FIND_E_ARG, "find_solve_scattering: nE must be >= 1");
+  if (!energies || !H || !sigma || !sigma_less || !sigma_d || !sigma_less_d || !diag_G || !diag_Gless)
+    return fail(FIND_E_ARG, "find_solve_scattering: NULL input or diagonal output pointer");
+  if (!plan->opts.scattering)
+    return fail(FIND_E_ARG, "find_solve_scattering: the plan was created without opts.scattering");
+  return solve_impl(plan, nE, energies, H, sigma, sigma_less, sigma_d, sigma_less_d, diag_G, diag_Gless, bond_G,
+                    bond_Gless, bond_J, hip_stream);
+}
+
 find_status find_plan_autotune(find_plan plan, int nE, const double* energies, const double* H,
                                const double* sigma, const double* sigma_less, double* diag_G,
                                double* diag_Gless, int reps, void* hip_stream) {
   if (!plan) return fail(FIND_E_ARG, "find_plan_autotune: NULL plan");
+  if (plan->opts.scattering)
+    return fail(FIND_E_UNSUPPORTED, "find_plan_autotune: not for scattering plans (set_tiles takes a tuned choice)");
   if (nE < 1) return fail(FIND_E_ARG, "find_plan_autotune: nE must be >= 1");
   if (!energies || !H || !sigma || !sigma_less || !diag_G || !diag_Gless)
     return fail(FIND_E_ARG, "find_plan_autotune: NULL input or output pointer");
@@ -614,6 +679,7 @@ find_status find_plan_autotune(find_plan plan, int nE, const double* energies, c
   StageArgs a;
   OutArgs o;
   pass_args(plan, d, 0, 0, ne, energies, H, sigma, sigma_less, diag_G, diag_Gless, nullptr, nullptr, nullptr, &a, &o);
+  if (launch_onsite(a, st) != hipSuccess) return fail(FIND_E_DEVICE, "find_plan_autotune: onsite launch");
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));

@@ -32,6 +32,9 @@ struct StageArgs {
   const double* H;        // [nst][Ny][Nx]
   const double2* sigma;   // sigma of this pass  [nE][2][Nx][Nx]
   const double2* sless;
+  const double2* sscat;   // diagonal scattering Sigma of this pass [nE][Ny][Nx], or NULL
+  const double2* slscat;  // and Sigma< (read by the node-diagonal pre-pass only)
+  long long onsite_off;   // pool offset (per energy) of the node diagonal E - H_ii - Sigma_d,i, then Sigma<_d,i
   double2* pool;          // pool of this pass, energy stride pool_stride
   long long pool_stride;
   double2* ws;            // per-slot workspace

@@ -161,7 +161,8 @@ struct Builder {
   // is supported on the contact columns y = 0 and y = Ny - 1 only, so
   // Sigma<(C, C) = 0, and so R = 0 for it and (recursively) for all its
   // descendants
-  bool up_rzero(const Cluster& c) const { return c.r.y0 > 0 && c.r.y0 + c.r.h < Ny; }
+  // (with diagonal scattering self-energies every node carries Sigma<, and no R vanishes)
+  bool up_rzero(const Cluster& c) const { return !P.scattering && c.r.y0 > 0 && c.r.y0 + c.r.h < Ny; }
 
   // Emit an elimination whose assembled node list is `list` (with per-entry
   // source and source position) and whose kept set is `keep` (in this order).
@@ -192,7 +193,7 @@ struct Builder {
     auto carries = [&](int k) -> bool {
       if (src[k] == SRC0 || src[k] == SRC1) return sig_src[src[k]] && (*sig_src[src[k]])[pos[k]];
       const int y = list[k] / Nx;
-      return y == 0 || y == Ny - 1;
+      return P.scattering || y == 0 || y == Ny - 1;
     };
     const auto mid = std::stable_partition(S_idx.begin(), S_idx.end(), carries);
     e.ssig = e.rzero ? 0 : int(mid - S_idx.begin());
@@ -357,6 +358,8 @@ struct Builder {
       leaf1_off[l] = off; off += 2 * bp * bp;
       fin_off[l] = off; off += 2 * bp * bp;
     }
+    P.onsite_off = off;
+    off += 2 * int64_t(Nx) * Ny;
     P.pool_per_energy = off;
     for (int v = 0; v < 2; ++v) {
       int first = int(P.elims.size());
@@ -446,9 +449,9 @@ struct Builder {
 
 }  // namespace
 
-std::string build_plan(int Nx, int Ny, int stencil, int leaf, Plan& P) {
+std::string build_plan(int Nx, int Ny, int stencil, int leaf, Plan& P, bool scattering) {
   P = Plan();
-  P.Nx = Nx; P.Ny = Ny; P.stencil = stencil; P.leaf = leaf;
+  P.Nx = Nx; P.Ny = Ny; P.stencil = stencil; P.leaf = leaf; P.scattering = scattering;
   Builder b(P);
   return b.build();
 }

@@ -55,6 +55,11 @@ struct OutBond { int bond, li, lj, k, hflat; };
 
 struct Plan {
   int Nx = 0, Ny = 0, stencil = 5, leaf = 8;
+  // diagonal scattering self-energies on every node: every node carries Sigma<
+  bool scattering = false;
+  // pool offset (per energy) of the node diagonal: A_ii of the original matrix
+  // without its contact part (E - H_ii - Sigma_d,i), then Sigma<_d,i ([2][Ny][Nx])
+  int64_t onsite_off = 0;
   std::vector<Cluster> cl;
   int depth = 0, n_leaves = 0;
   std::vector<Elim> elims;
@@ -72,7 +77,7 @@ struct Plan {
 
 int count_bonds(int Nx, int Ny, int stencil);
 // Builds the plan; returns an empty string on success, else a message.
-std::string build_plan(int Nx, int Ny, int stencil, int leaf, Plan& P);
+std::string build_plan(int Nx, int Ny, int stencil, int leaf, Plan& P, bool scattering = false);
 // sym: bit 0 = only half of U formed, bit 1 = only half of R formed
 double elim_flops(const Elim& e, int sym = 0);
 

@@ -23,7 +23,7 @@ EF_FIELDS, SF_FIELDS, LF_FIELDS, ON_FIELDS, OB_FIELDS = 17, 4, 6, 2, 5
 EXPORTED = ["find_plan_create", "find_plan_destroy", "find_plan_footprint", "find_plan_flops",
             "find_n_bonds", "find_solve", "find_sync_status", "find_last_error",
             "find_plan_summary", "find_plan_export", "find_plan_set_profiling", "find_plan_profile",
-            "find_plan_autotune", "find_plan_get_tiles", "find_plan_set_tiles"]
+            "find_plan_autotune", "find_plan_get_tiles", "find_plan_set_tiles", "find_solve_scattering"]
 
 
 class FindError(RuntimeError):
@@ -36,7 +36,7 @@ class PlanOpts(ctypes.Structure):
     _fields_ = [("leaf", ctypes.c_int), ("precision", ctypes.c_int), ("max_energies", ctypes.c_int),
                 ("fp64_top_levels", ctypes.c_int), ("workspace_budget", ctypes.c_size_t),
                 ("complex_mode", ctypes.c_int), ("symmetric", ctypes.c_int), ("streams", ctypes.c_int),
-                ("reserved", ctypes.c_int * 5)]
+                ("scattering", ctypes.c_int), ("reserved", ctypes.c_int * 4)]
 
 
 class PlanSummary(ctypes.Structure):
@@ -72,6 +72,8 @@ def lib() -> ctypes.CDLL:
         L.find_n_bonds.argtypes = [i32, i32, i32]; L.find_n_bonds.restype = i32
         L.find_solve.argtypes = [vp, i32] + [vp] * 9 + [vp]
         L.find_solve.restype = st
+        L.find_solve_scattering.argtypes = [vp, i32] + [vp] * 11 + [vp]
+        L.find_solve_scattering.restype = st
         L.find_sync_status.argtypes = [vp, vp]; L.find_sync_status.restype = st
         L.find_last_error.argtypes = []; L.find_last_error.restype = ctypes.c_char_p
         L.find_plan_summary.argtypes = [vp, ctypes.POINTER(PlanSummary)]; L.find_plan_summary.restype = st
@@ -102,12 +104,15 @@ class Plan:
 
     def __init__(self, Nx: int, Ny: int, stencil: int = 5, leaf: int = 8, precision: int = PREC_FP64,
                  max_energies: int = 0, workspace_budget: int = 0, fp64_top_levels: int = 0,
-                 complex_mode: int = CPLX_4M, symmetric: bool = False, streams: int = 0):
+                 complex_mode: int = CPLX_4M, symmetric: bool = False, streams: int = 0,
+                 scattering: bool = False):
         self.Nx, self.Ny, self.stencil = Nx, Ny, stencil
+        self.scattering = bool(scattering)
         self._h = ctypes.c_void_p()
         o = PlanOpts(leaf=leaf, precision=precision, max_energies=max_energies,
                      workspace_budget=workspace_budget, fp64_top_levels=fp64_top_levels,
-                     complex_mode=complex_mode, symmetric=int(bool(symmetric)), streams=streams)
+                     complex_mode=complex_mode, symmetric=int(bool(symmetric)), streams=streams,
+                     scattering=int(bool(scattering)))
         _check(lib().find_plan_create(Nx, Ny, stencil, ctypes.byref(o), ctypes.byref(self._h)))
 
     def close(self):
@@ -198,12 +203,14 @@ def _ptr(t, name, shape, dtype):
 
 
 def solve(plan: Plan, energies, H, sigma, sigma_less, diag_G, diag_Gless,
-          bond_G=None, bond_Gless=None, bond_J=None, stream=None) -> None:
+          bond_G=None, bond_Gless=None, bond_J=None, stream=None, sigma_d=None, sigma_less_d=None) -> None:
     """Enqueue one FIND solve on `stream` (default: torch's current stream).
 
     energies complex128 [nE]; H float64 [nst][Ny][Nx]; sigma, sigma_less complex128
     [nE][2][Nx][Nx]; diag_G, diag_Gless complex128 [nE][Ny][Nx]; optional
     bond_G, bond_Gless complex128 [nE][nbonds] and bond_J float64 [nE][nbonds].
+    For a plan created with scattering=True, sigma_d and sigma_less_d complex128
+    [nE][Ny][Nx] (diagonal scattering self-energies) are required.
     """
     import torch
     Nx, Ny = plan.Nx, plan.Ny
@@ -219,7 +226,13 @@ def solve(plan: Plan, energies, H, sigma, sigma_less, diag_G, diag_Gless,
     if stream is None:
         stream = torch.cuda.current_stream()
     sp = ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
-    _check(lib().find_solve(plan.handle, nE, *args, sp))
+    if plan.scattering:
+        if sigma_d is None or sigma_less_d is None:
+            raise ValueError("a scattering plan needs sigma_d and sigma_less_d")
+        d = [_ptr(sigma_d, "sigma_d", (nE, Ny, Nx), c128), _ptr(sigma_less_d, "sigma_less_d", (nE, Ny, Nx), c128)]
+        _check(lib().find_solve_scattering(plan.handle, nE, *args[:4], *d, *args[4:], sp))
+    else:
+        _check(lib().find_solve(plan.handle, nE, *args, sp))
 
 
 def autotune(plan: Plan, energies, H, sigma, sigma_less, diag_G, diag_Gless, reps: int = 2,
@@ -267,7 +280,11 @@ def run_problem(plan: Plan, prob: dict, want_bonds: bool = True, device: str = "
         out.update(bond_G=torch.empty((nE, nb), dtype=torch.complex128, device=dev),
                    bond_Gless=torch.empty((nE, nb), dtype=torch.complex128, device=dev),
                    bond_J=torch.empty((nE, nb), dtype=torch.float64, device=dev))
+    extra = {}
+    if "sigma_d" in prob:
+        extra = dict(sigma_d=torch.as_tensor(np.ascontiguousarray(prob["sigma_d"]), device=dev),
+                     sigma_less_d=torch.as_tensor(np.ascontiguousarray(prob["sigma_less_d"]), device=dev))
     solve(plan, E, H, S, SL, out["diag_G"], out["diag_Gless"], out.get("bond_G"), out.get("bond_Gless"),
-          out.get("bond_J"))
+          out.get("bond_J"), **extra)
     sync_status(plan)
     return {k: v.cpu().numpy() for k, v in out.items()}

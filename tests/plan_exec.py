@@ -16,11 +16,17 @@ import numpy as np
 K_FINAL = 1
 
 
-def orig_entries(nodes_r, nodes_c, Nx, Ny, Hm, E, sig, sless):
-    """Original A and Sigma< entries between two node lists (dense lookup)."""
+def orig_entries(nodes_r, nodes_c, Nx, Ny, Hm, E, sig, sless, sd=None, sld=None):
+    """Original A and Sigma< entries between two node lists (dense lookup);
+    sd, sld: diagonal scattering self-energies per node (flat), or None."""
     A = -Hm[np.ix_(nodes_r, nodes_c)].astype(np.complex128)
-    A += E * (nodes_r[:, None] == nodes_c[None, :])
+    same = nodes_r[:, None] == nodes_c[None, :]
+    A += E * same
     S = np.zeros_like(A)
+    if sd is not None:
+        A -= np.where(same, sd[nodes_r][:, None], 0)
+    if sld is not None:
+        S += np.where(same, sld[nodes_r][:, None], 0)
     xr, yr = nodes_r % Nx, nodes_r // Nx
     xc, yc = nodes_c % Nx, nodes_c // Nx
     for c, ycol in ((0, 0), (1, Ny - 1)):
@@ -31,7 +37,8 @@ def orig_entries(nodes_r, nodes_c, Nx, Ny, Hm, E, sig, sless):
     return A, S
 
 
-def execute(plan_export: dict, Nx, Ny, stencil, Hm, E, sig, sless, want_bonds=True, record=None, fronts=None):
+def execute(plan_export: dict, Nx, Ny, stencil, Hm, E, sig, sless, want_bonds=True, record=None, fronts=None,
+            sd=None, sld=None):
     ex = plan_export
     elims, maps, stages = ex["elims"], ex["maps"], ex["stages"]
     variant = 1 if want_bonds else 0
@@ -48,7 +55,7 @@ def execute(plan_export: dict, Nx, Ny, stencil, Hm, E, sig, sless, want_bonds=Tr
                 G = np.linalg.inv(U0)
                 pool[dst] = (-G, G @ R0 @ G.conj().T)
                 continue
-            A, S = orig_entries(node, node, Nx, Ny, Hm, E, sig, sless)
+            A, S = orig_entries(node, node, Nx, Ny, Hm, E, sig, sless, sd, sld)
             for sid, off in ((0, src0), (1, src1)):
                 sel = np.where(src == sid)[0]
                 if sel.size:

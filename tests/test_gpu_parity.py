@@ -317,6 +317,27 @@ def test_mixed_gless_c2_and_c3_sampled():
     assert max(eg) <= TOL and max(el) <= 1e-4, (max(eg), max(el))
 
 
+@pytest.mark.parametrize("Nx,Ny,stencil,leaf", [(16, 16, 5, 4), (12, 9, 9, 4), (24, 30, 9, 8), (1, 11, 5, 2),
+                                                (40, 40, 5, 8)])
+def test_scattering_self_energies_against_dense(Nx, Ny, stencil, leaf):
+    """Diagonal scattering self-energies on every node (find_solve_scattering),
+    general and symmetric forms, with bond outputs."""
+    f = find()
+    E = np.array([0.41 + 1e-6j, -2.9 + 1e-6j, 1.3 + 1e-3j])
+    prob = inputs.make_problem(Nx, Ny, stencil, vmax=1.0, seed=Nx * 17 + Ny, energies=E, fL=1.0, fR=0.3)
+    sd, sl = inputs.scattering_self_energies(Nx, Ny, E.size, gamma=0.05, f=0.6, seed=Ny)
+    prob.update(sigma_d=sd, sigma_less_d=sl)
+    ref = dense.dense_solve(Nx, Ny, stencil, prob["H"], E, prob["sigma"], prob["sigma_less"],
+                            sigma_d=sd, sigma_less_d=sl)
+    for sym in (False, True):
+        plan = f.Plan(Nx, Ny, stencil, leaf=leaf, scattering=True, symmetric=sym)
+        out = f.run_problem(plan, prob, want_bonds=True)
+        compare(out, ref, prob, label=f"scattering {Nx}x{Ny} sym={sym}")
+        if sym:
+            dG = f.run_problem(plan, prob, want_bonds=False)
+            compare(dG, ref, prob, bonds=False, label=f"scattering diag {Nx}x{Ny}")
+
+
 def test_concurrent_energy_groups_match_one_stream():
     """Energy groups on the plan's own streams give the same bits as one stream
     (also with several passes and the bond outputs)."""

@@ -49,6 +49,23 @@ def test_argument_errors():
     assert b"NULL plan" in L.find_last_error()
 
 
+def test_scattering_entry_points_reject_the_other_kind_of_plan():
+    """find_solve refuses a scattering plan and find_solve_scattering a plain
+    one (argument checks only: no device work, dummy pointers never read)."""
+    find = findlib()
+    L = find.lib()
+    dummy = [ctypes.c_void_p(16)] * 11
+    sp = find.Plan(6, 6, 5, scattering=True)
+    pp = find.Plan(6, 6, 5)
+    assert L.find_solve(sp.handle, 1, *dummy[:9], None) == find.FIND_E_ARG
+    assert L.find_solve_scattering(pp.handle, 1, *dummy, None) == find.FIND_E_ARG
+    assert L.find_solve_scattering(sp.handle, 1, *dummy[:4], None, *dummy[5:], None) == find.FIND_E_ARG
+    assert L.find_solve_scattering(sp.handle, 1, *dummy[:5], None, *dummy[6:], None) == find.FIND_E_ARG
+    o = find.PlanOpts(leaf=8, scattering=2)
+    h = ctypes.c_void_p()
+    assert L.find_plan_create(6, 6, 5, ctypes.byref(o), ctypes.byref(h)) == find.FIND_E_ARG
+
+
 def test_tile_and_complex_mode_options():
     find = findlib()
     with pytest.raises(find.FindError) as ei:
@@ -257,3 +274,37 @@ def test_plan_executor_matches_oracle(Nx, Ny, stencil, leaf, want_bonds):
         H = prob["H"]
         J = np.array([2 * np.real(H[bJ[k][2]].ravel()[bJ[k][3]] * bJ[k][4]) for k in range(nb)])
         assert np.max(np.abs(J - ref["bond_J"][0])) < 1e-10 * (np.max(np.abs(ref["bond_J"][0])) + 1e-3)
+
+
+@pytest.mark.parametrize("Nx,Ny,stencil,leaf", [(12, 9, 9, 4), (16, 16, 5, 8), (7, 13, 5, 3)])
+def test_scattering_plan_executor_matches_oracle(Nx, Ny, stencil, leaf):
+    """A plan for diagonal scattering self-energies (every node carries Sigma<:
+    no front flagged R = 0, every eliminated node in the Sigma prefix) gives
+    the oracle's outputs through the definition-level executor, and its
+    assembled fronts keep the zeros the flags promise."""
+    from tests.plan_exec import execute
+    find = findlib()
+    E = 0.41 + 1e-3j
+    prob = inputs.make_problem(Nx, Ny, stencil, vmax=0.8, seed=Nx * 7 + Ny, energies=[E], fL=1.0, fR=0.2)
+    sd, sl = inputs.scattering_self_energies(Nx, Ny, 1, gamma=0.06, f=0.3, seed=5)
+    p = find.Plan(Nx, Ny, stencil, leaf=leaf, scattering=True)
+    ex = p.export()
+    el = ex["elims"]
+    schur = el[el[:, 0] == 0]
+    assert not np.any(schur[:, 13]) and np.all(schur[:, 14] == schur[:, 1])
+    Hm = dense.hamiltonian_matrix(Nx, Ny, prob["H"])
+    fronts = {}
+    dG, dL, bG, bL, bJ = execute(ex, Nx, Ny, stencil, Hm, E, prob["sigma"][0], prob["sigma_less"][0], True,
+                                 fronts=fronts, sd=sd[0].reshape(-1), sld=sl[0].reshape(-1))
+    ref = dense.dense_solve(Nx, Ny, stencil, prob["H"], prob["energies"], prob["sigma"], prob["sigma_less"],
+                            sigma_d=sd, sigma_less_d=sl)
+    assert np.max(np.abs(dG - ref["diag_G"][0])) < 1e-11 * np.max(np.abs(ref["diag_G"][0]))
+    assert np.max(np.abs(dL - ref["diag_Gless"][0])) < 1e-11 * np.max(np.abs(ref["diag_Gless"][0]))
+    nb = inputs.n_bonds(Nx, Ny, stencil)
+    l = np.array([bL[k] for k in range(nb)])
+    assert np.max(np.abs(l - ref["bond_Gless"][0])) < 1e-11 * np.max(np.abs(ref["bond_Gless"][0]))
+    for k, (Ag, Sg) in fronts.items():
+        s_, b_, ba = el[k][1], el[k][2], el[k][16]
+        na = s_ + ba
+        for M in (Ag, Sg):
+            assert np.all(M[na:, :s_] == 0) and np.all(M[:s_, na:] == 0), k

@@ -336,6 +336,12 @@ def test_scattering_self_energies_against_dense(Nx, Ny, stencil, leaf):
         if sym:
             dG = f.run_problem(plan, prob, want_bonds=False)
             compare(dG, ref, prob, bonds=False, label=f"scattering diag {Nx}x{Ny}")
+    # several passes and energy groups: each group writes its own node diagonal
+    one = f.run_problem(f.Plan(Nx, Ny, stencil, leaf=leaf, scattering=True), prob, want_bonds=True)
+    grp = f.run_problem(f.Plan(Nx, Ny, stencil, leaf=leaf, scattering=True, streams=2, max_energies=2), prob,
+                        want_bonds=True)
+    for k in one:
+        assert np.array_equal(grp[k], one[k]), k
 
 
 def test_concurrent_energy_groups_match_one_stream():

@@ -29,8 +29,8 @@ PRECISION = {"fp64": 0, "mixed": 1, "mixed-gless": 2}   # find_precision values
 # solve, from rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs (calibrated on a
 # plain copy; profiles/elim_kernels_c3_128x128_fp64.md).  Valid only for the
 # native sources (kernels, plan, C-ABI) they were measured on.
-TRAFFIC_BYTES_PER_LAUNCH = 19994449240.5
-TRAFFIC_KERNEL_SHA = "bee350cb2b0a2f52"
+TRAFFIC_BYTES_PER_LAUNCH = 20003128067.34
+TRAFFIC_KERNEL_SHA = "27b396333fcd6b9d"
 TRAFFIC_TILES = "44551176370111555500"
 TRAFFIC_FORM = (True, 2)   # (symmetric, energy groups) of the counter runs
 

@@ -154,6 +154,9 @@ def main() -> int:
     ap.add_argument("--streams", type=int, default=2, help="energy groups solved concurrently (0/1 = one)")
     ap.add_argument("--autotune", action="store_true",
                     help="run the autotuner even if the tuning table has an entry for this workload")
+    ap.add_argument("--scattering", action="store_true",
+                    help="add diagonal scattering self-energies on every node (dephasing probes, gamma = 0.05) "
+                         "and solve with find_solve_scattering")
     ap.add_argument("--tiles", default="",
                     help="fixed wave tile per stage (one digit per stage, as reported in config.stage_tiles); "
                          "skips the autotuner")
@@ -193,10 +196,14 @@ def main() -> int:
     SL = torch.as_tensor(prob["sigma_less"], device=dev)
     dG = torch.empty((nE, Ny, Nx), dtype=torch.complex128, device=dev)
     dL = torch.empty_like(dG)
+    scat = {}
+    if args.scattering:
+        sd, sl = inputs.scattering_self_energies(Nx, Ny, nE, gamma=0.05, f=0.5, seed=0)
+        scat = dict(sigma_d=torch.as_tensor(sd, device=dev), sigma_less_d=torch.as_tensor(sl, device=dev))
     prec = PRECISION[args.precision]
     cmode = find.CPLX_3M if args.complex_mode == "3m" else find.CPLX_4M
     plan = find.Plan(Nx, Ny, st, leaf=args.leaf, precision=prec, complex_mode=cmode, symmetric=not args.general,
-                     streams=args.streams)
+                     streams=args.streams, scattering=args.scattering)
     plain_flops = plain_find_flops(plan)
     stream = torch.cuda.Stream()          # non-default stream (graph capture needs one)
     torch.cuda.set_stream(stream)
@@ -204,6 +211,15 @@ def main() -> int:
     key = f"{Nx}x{Ny}/{st}/{args.leaf}/{args.precision}/{args.complex_mode}" + ("" if args.general else "/sym")
     table = json.load(open(os.path.join(ROOT, "paper_1104_0623_amd", "tuning.json")))
     tiles_from = "autotune"
+    if args.scattering:
+        # the tree and fronts are those of the contacts-only plan (the autotuner
+        # takes no scattering inputs): its tuned tiles unless a scattering entry exists
+        if key + "/scat" in table:
+            key += "/scat"
+        if args.autotune:
+            raise SystemExit("bench.py: --autotune does not take scattering inputs; use --tiles")
+        if not args.tiles and not args.no_autotune and key not in table:
+            args.no_autotune = True
     if not args.tiles and not args.autotune and not args.no_autotune and key in table:
         args.tiles, tiles_from = table[key], "tuning table"
     if args.tiles:
@@ -220,7 +236,7 @@ def main() -> int:
     tiles = plan.tiles()
 
     def eager_step():
-        find.solve(plan, E, H, S, SL, dG, dL, stream=stream)
+        find.solve(plan, E, H, S, SL, dG, dL, stream=stream, **scat)
 
     for _ in range(max(1, args.warmup)):
         eager_step()
@@ -275,7 +291,9 @@ def main() -> int:
         "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"FIND diag G + diag G<, {Nx}x{Ny} mesh, {st}-point stencil, {nE} energies "
-                               f"per step ({args.preset}), {args.precision}",
+                               f"per step ({args.preset}), {args.precision}"
+                               + (", diagonal scattering self-energies on every node" if args.scattering else ""),
+                   "scattering": bool(args.scattering),
                    "Nx": Nx, "Ny": Ny, "stencil": st, "energies_per_step": nE, "precision": args.precision,
                    "leaf": args.leaf, "complex_mode": args.complex_mode, "symmetric": not args.general, "streams": args.streams,
                    "launch": "eager" if args.no_graph else "hipGraph replay per batch",
@@ -284,7 +302,7 @@ def main() -> int:
                    "autotune_s": round(tune_s, 3) if tiles_from == "autotune" else None},
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": measured_traffic(args.preset, args.precision, "".join(str(t) for t in tiles),
+                     "frac": achieved / peak, "traffic": None if args.scattering else measured_traffic(args.preset, args.precision, "".join(str(t) for t in tiles),
                                                                  args.complex_mode,
                                                                  (not args.general, max(1, args.streams))),
                      "kernel": "k_stage + k_final (elimination kernels, all stage launches)",
@@ -299,9 +317,9 @@ def main() -> int:
     }
     if args.precision != "fp64":
         # error of this result against the FP64 form of the same solve, per energy
-        ref = find.Plan(Nx, Ny, st, precision=find.PREC_FP64)
+        ref = find.Plan(Nx, Ny, st, precision=find.PREC_FP64, scattering=args.scattering)
         rG = torch.empty_like(dG); rL = torch.empty_like(dL)
-        find.solve(ref, E, H, S, SL, rG, rL, stream=stream)
+        find.solve(ref, E, H, S, SL, rG, rL, stream=stream, **scat)
         find.sync_status(ref, stream)
         def nerr(x, r):
             x, r = x.reshape(nE, -1), r.reshape(nE, -1)
@@ -311,7 +329,8 @@ def main() -> int:
                                       "diag_G_median": float(np.median(eg)),
                                       "diag_Gless_median": float(np.median(el)),
                                       "metric": "per energy ||x - x_fp64||_inf / ||x_fp64||_inf"}
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not args.scattering:
+        # (the RGF oracle takes contact self-energies only: no CPU figure for --scattering)
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)
     return 0

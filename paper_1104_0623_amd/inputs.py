@@ -127,7 +127,7 @@ def scattering_self_energies(Nx: int, Ny: int, nE: int, gamma: float = 0.05, f: 
     Sigma<_d = -f (Sigma_d - Sigma_d^*) = i f gamma_i.  Arrays [nE][Ny][Nx]."""
     rng = np.random.default_rng(seed)
     g = rng.uniform(0.5 * gamma, 1.5 * gamma, size=Nx * Ny).reshape(Ny, Nx)
-    sd = np.broadcast_to(-0.5j * g, (nE, Ny, Nx)).astype(np.complex128)
+    sd = np.ascontiguousarray(np.broadcast_to(-0.5j * g, (nE, Ny, Nx)), dtype=np.complex128)
     sl = -f * (sd - sd.conj())
     return sd, np.ascontiguousarray(sl)
 

@@ -336,6 +336,12 @@ def test_scattering_self_energies_against_dense(Nx, Ny, stencil, leaf):
         if sym:
             dG = f.run_problem(plan, prob, want_bonds=False)
             compare(dG, ref, prob, bonds=False, label=f"scattering diag {Nx}x{Ny}")
+    # the G<-only mixed form (Sigma products in FP32) with every node carrying Sigma<
+    mg = f.run_problem(f.Plan(Nx, Ny, stencil, leaf=leaf, scattering=True, symmetric=True,
+                              precision=f.PREC_MIXED_GLESS), prob, want_bonds=False)
+    for e in range(E.size):
+        assert nrel(mg["diag_G"][e], ref["diag_G"][e]) <= TOL, ("mixed-gless scattering diag_G", e)
+        assert nrel(mg["diag_Gless"][e], ref["diag_Gless"][e]) <= GLESS_TOL, ("mixed-gless scattering diag_Gless", e)
     # several passes and energy groups: each group writes its own node diagonal
     one = f.run_problem(f.Plan(Nx, Ny, stencil, leaf=leaf, scattering=True), prob, want_bonds=True)
     grp = f.run_problem(f.Plan(Nx, Ny, stencil, leaf=leaf, scattering=True, streams=2, max_energies=2), prob,

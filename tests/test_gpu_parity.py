@@ -103,6 +103,33 @@ def test_c3_128x128_sampled_energies_against_rgf():
     assert np.min(dl.imag) >= -1e-9 * np.max(np.abs(dl))
 
 
+def test_c3_128x128_scattering_sampled_against_rgf():
+    """Full 128 x 128 mesh with diagonal scattering self-energies on every
+    node, in the benchmark's launch configuration (symmetric form, two
+    energy groups, the tuning table's tiles); the oracle computes a sample of
+    the energies one by one."""
+    import json, os
+    f = find()
+    prob = inputs.make_preset("c3_128x128")
+    nE = prob["energies"].size
+    sd, sl = inputs.scattering_self_energies(128, 128, nE, gamma=0.05, f=0.5, seed=0)
+    prob.update(sigma_d=sd, sigma_less_d=sl)
+    plan = f.Plan(128, 128, 5, symmetric=True, streams=2, scattering=True)
+    table = json.load(open(os.path.join(os.path.dirname(f.__file__), "tuning.json")))
+    plan.set_tiles([int(c) for c in table["128x128/5/8/fp64/4m/sym"]])
+    out = f.run_problem(plan, prob, want_bonds=False)
+    sample = [3, 128, 250]
+    sub = {k: v[sample] for k, v in prob.items() if k in ("energies", "sigma", "sigma_less", "sigma_d", "sigma_less_d")}
+    ref = rgf.rgf_solve(128, 128, 5, prob["H"], sub["energies"], sub["sigma"], sub["sigma_less"], bonds=False,
+                        sigma_d=sub["sigma_d"], sigma_less_d=sub["sigma_less_d"])
+    for q, e in enumerate(sample):
+        assert nrel(out["diag_G"][e], ref["diag_G"][q]) <= TOL, e
+        assert nrel(out["diag_Gless"][e], ref["diag_Gless"][q]) <= TOL, e
+    dl = out["diag_Gless"]
+    assert np.max(np.abs(dl.real)) <= 1e-9 * np.max(np.abs(dl))
+    assert np.min(dl.imag) >= -1e-9 * np.max(np.abs(dl))
+
+
 def test_deterministic_and_chunk_invariant():
     f = find()
     E = inputs.energies_linspace(-3.0, 3.0, 7)

@@ -86,6 +86,30 @@ def test_rgf_matches_dense(Nx, Ny, stencil, seed):
         assert np.max(np.abs(r["bond_J"][e] - d["bond_J"][e])) <= 1e-10 * scale
 
 
+@pytest.mark.parametrize("Nx,Ny,stencil,seed", [(8, 7, 5, 21), (6, 9, 9, 22), (1, 6, 5, 23), (5, 1, 9, 24),
+                                                (4, 4, 5, 25)])
+def test_rgf_with_scattering_matches_dense(Nx, Ny, stencil, seed):
+    """The RGF lesser recursion with Sigma< on every column (diagonal
+    scattering self-energies) against the dense definition; also the contacts-
+    only sweep when the scattering terms vanish."""
+    E = np.array([0.3 + 1e-6j, -2.1 + 1e-6j, 1.7 + 1e-3j])
+    p = inputs.make_problem(Nx, Ny, stencil, vmax=1.0, seed=seed, energies=E, fL=1.0, fR=0.25)
+    if stencil == 9:
+        # unequal diagonal hoppings: the inter-column blocks are not symmetric
+        p["H"][3:] *= 1.0 + 0.4 * np.random.default_rng(seed).standard_normal(p["H"][3:].shape)
+    sd, sl = inputs.scattering_self_energies(Nx, Ny, E.size, gamma=0.07, f=0.6, seed=seed)
+    d = dense.dense_solve(Nx, Ny, stencil, p["H"], E, p["sigma"], p["sigma_less"], sigma_d=sd, sigma_less_d=sl)
+    r = rgf.rgf_solve(Nx, Ny, stencil, p["H"], E, p["sigma"], p["sigma_less"], sigma_d=sd, sigma_less_d=sl)
+    for k in ("diag_G", "diag_Gless", "bond_G", "bond_Gless"):
+        for e in range(E.size):
+            assert rel(r[k][e], d[k][e]) < 1e-10, k
+    z = np.zeros_like(sd)
+    r0 = rgf.rgf_solve(Nx, Ny, stencil, p["H"], E, p["sigma"], p["sigma_less"], sigma_d=z, sigma_less_d=z)
+    c0 = rgf.rgf_solve(Nx, Ny, stencil, p["H"], E, p["sigma"], p["sigma_less"])
+    for k in ("diag_G", "diag_Gless", "bond_G", "bond_Gless"):
+        assert rel(r0[k], c0[k]) < 1e-11, k
+
+
 def test_identities_symmetry_and_antihermitian():
     Nx, Ny, stencil = 5, 6, 9
     E = np.array([0.45 + 1e-6j])

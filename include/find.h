@@ -220,16 +220,21 @@ find_status find_plan_profile(find_plan plan, double* kernel_ms, double* kernel_
  * 6 = one 256-thread workgroup per front with 64x64 workgroup tiles whose
  * operands the four waves share through LDS, for the Schur products and the
  * LU trailing updates (stages whose fronts have at most 512 nodes, not the
- * final leaf blocks).
+ * final leaf blocks); 7 = one 512-thread workgroup (eight waves) per front and
+ * one workgroup per compute unit, for stages with few large fronts (fronts of
+ * up to 2048 nodes, not the final leaf blocks).
  * Configurations 0..3 and 6 only decide which threads compute which part of
  * the same operations in the same order, so their results are bitwise the
- * same; 4 and 5 factor fronts with narrower register panels (same
+ * same; 4, 5 and 7 factor fronts with other register panels (same
  * operations, other rounding).
  *   find_plan_autotune runs one solve of the first min(nE, pass size)
  *   energies stage by stage, times every configuration of every stage `reps`
  *   times (reps < 1 means 2) with HIP events on `hip_stream`, keeps the
  *   fastest, and leaves that solve's diag G / diag G< in the outputs.  It
- *   synchronises the stream; FIND_E_ARG if the stream is being captured.
+ *   synchronises the stream; FIND_E_ARG if the stream is being captured,
+ *   FIND_E_UNSUPPORTED for a scattering plan (it takes no scattering
+ *   inputs; such a plan has the stages of the contacts-only plan of the same
+ *   mesh and options, whose tuned configurations find_plan_set_tiles takes).
  *   find_plan_get_tiles copies min(cap, n_stages) configurations (stage
  *   order of find_plan_export) to tiles and the bit mask of the
  *   configurations each stage has to masks (either may be NULL), and stores

@@ -29,8 +29,8 @@ PRECISION = {"fp64": 0, "mixed": 1, "mixed-gless": 2}   # find_precision values
 # solve, from rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs (calibrated on a
 # plain copy; profiles/elim_kernels_c3_128x128_fp64.md).  Valid only for the
 # native sources (kernels, plan, C-ABI) they were measured on.
-TRAFFIC_BYTES_PER_LAUNCH = 20003128067.34
-TRAFFIC_KERNEL_SHA = "27b396333fcd6b9d"
+TRAFFIC_BYTES_PER_LAUNCH = 20000807120.13
+TRAFFIC_KERNEL_SHA = "493a9af9fa160391"
 TRAFFIC_TILES = "44551176370111555500"
 TRAFFIC_FORM = (True, 2)   # (symmetric, energy groups) of the counter runs
 
@@ -214,12 +214,10 @@ def main() -> int:
     table = json.load(open(os.path.join(ROOT, "paper_1104_0623_amd", "tuning.json")))
     tiles_from = "autotune"
     if args.scattering:
-        # the tree and fronts are those of the contacts-only plan (the autotuner
-        # takes no scattering inputs): its tuned tiles unless a scattering entry exists
+        # the tree and fronts are those of the contacts-only plan: its tuned
+        # tiles unless a scattering entry exists
         if key + "/scat" in table:
             key += "/scat"
-        if args.autotune:
-            raise SystemExit("bench.py: --autotune does not take scattering inputs; use --tiles")
         if not args.tiles and not args.no_autotune and key not in table:
             args.no_autotune = True
     if not args.tiles and not args.autotune and not args.no_autotune and key in table:

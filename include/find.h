@@ -231,10 +231,10 @@ find_status find_plan_profile(find_plan plan, double* kernel_ms, double* kernel_
  *   energies stage by stage, times every configuration of every stage `reps`
  *   times (reps < 1 means 2) with HIP events on `hip_stream`, keeps the
  *   fastest, and leaves that solve's diag G / diag G< in the outputs.  It
- *   synchronises the stream; FIND_E_ARG if the stream is being captured,
- *   FIND_E_UNSUPPORTED for a scattering plan (it takes no scattering
- *   inputs; such a plan has the stages of the contacts-only plan of the same
- *   mesh and options, whose tuned configurations find_plan_set_tiles takes).
+ *   synchronises the stream; FIND_E_ARG if the stream is being captured.
+ *   A scattering plan is tuned on a solve with zero scattering self-energies
+ *   (the same work: such a plan forms W and R on every front whatever their
+ *   values), whose results the outputs then hold.
  *   find_plan_get_tiles copies min(cap, n_stages) configurations (stage
  *   order of find_plan_export) to tiles and the bit mask of the
  *   configurations each stage has to masks (either may be NULL), and stores

@@ -658,8 +658,6 @@ find_status find_plan_autotune(find_plan plan, int nE, const double* energies, c
                                const double* sigma, const double* sigma_less, double* diag_G,
                                double* diag_Gless, int reps, void* hip_stream) {
   if (!plan) return fail(FIND_E_ARG, "find_plan_autotune: NULL plan");
-  if (plan->opts.scattering)
-    return fail(FIND_E_UNSUPPORTED, "find_plan_autotune: not for scattering plans (set_tiles takes a tuned choice)");
   if (nE < 1) return fail(FIND_E_ARG, "find_plan_autotune: nE must be >= 1");
   if (!energies || !H || !sigma || !sigma_less || !diag_G || !diag_Gless)
     return fail(FIND_E_ARG, "find_plan_autotune: NULL input or output pointer");

@@ -369,6 +369,23 @@ def test_scattering_self_energies_against_dense(Nx, Ny, stencil, leaf):
     for e in range(E.size):
         assert nrel(mg["diag_G"][e], ref["diag_G"][e]) <= TOL, ("mixed-gless scattering diag_G", e)
         assert nrel(mg["diag_Gless"][e], ref["diag_Gless"][e]) <= GLESS_TOL, ("mixed-gless scattering diag_Gless", e)
+    if Nx * Ny >= 256:
+        # a scattering plan tunes on a solve with zero scattering self-energies:
+        # its outputs are the contacts-only results, and the tuned plan keeps parity
+        import torch
+        tp = f.Plan(Nx, Ny, stencil, leaf=leaf, scattering=True, symmetric=True)
+        dev = torch.device("cuda")
+        t = {k: torch.as_tensor(np.ascontiguousarray(prob[k]), device=dev)
+             for k in ("energies", "H", "sigma", "sigma_less")}
+        dG = torch.zeros((E.size, Ny, Nx), dtype=torch.complex128, device=dev)
+        dL = torch.zeros_like(dG)
+        tiles = f.autotune(tp, t["energies"], t["H"], t["sigma"], t["sigma_less"], dG, dL, reps=1)
+        assert all(tc in o for tc, o in zip(tiles, tp.tile_options()))
+        plain = dense.dense_solve(Nx, Ny, stencil, prob["H"], E, prob["sigma"], prob["sigma_less"])
+        for e in range(E.size):
+            assert nrel(dG[e].cpu().numpy(), plain["diag_G"][e]) <= TOL, ("autotune solve diag_G", e)
+            assert nrel(dL[e].cpu().numpy(), plain["diag_Gless"][e]) <= TOL, ("autotune solve diag_Gless", e)
+        compare(f.run_problem(tp, prob, want_bonds=True), ref, prob, label=f"tuned scattering {Nx}x{Ny}")
     # several passes and energy groups: each group writes its own node diagonal
     one = f.run_problem(f.Plan(Nx, Ny, stencil, leaf=leaf, scattering=True), prob, want_bonds=True)
     grp = f.run_problem(f.Plan(Nx, Ny, stencil, leaf=leaf, scattering=True, streams=2, max_energies=2), prob,

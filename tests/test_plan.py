@@ -61,8 +61,6 @@ def test_scattering_entry_points_reject_the_other_kind_of_plan():
     assert L.find_solve_scattering(pp.handle, 1, *dummy, None) == find.FIND_E_ARG
     assert L.find_solve_scattering(sp.handle, 1, *dummy[:4], None, *dummy[5:], None) == find.FIND_E_ARG
     assert L.find_solve_scattering(sp.handle, 1, *dummy[:5], None, *dummy[6:], None) == find.FIND_E_ARG
-    # the autotuner takes no scattering inputs: scattering plans get tiles by set_tiles
-    assert L.find_plan_autotune(sp.handle, 1, *dummy[:6], 2, None) == find.FIND_E_UNSUPPORTED
     o = find.PlanOpts(leaf=8, scattering=2)
     h = ctypes.c_void_p()
     assert L.find_plan_create(6, 6, 5, ctypes.byref(o), ctypes.byref(h)) == find.FIND_E_ARG

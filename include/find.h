@@ -24,6 +24,9 @@
  *              symmetric (the stored value is used for both H_ij and H_ji).
  *   energies   complex [nE]   (E + i*eta, eta > 0)
  *   sigma      complex [nE][2][Nx][Nx]: sigma[e][c][a][b] = Sigma_c(row a, col b)
+ *              (row-major inside each contact block; for the complex
+ *              symmetric leads of a real transverse basis this equals the
+ *              column-major layout)
  *   sigma_less complex [nE][2][Nx][Nx], same layout (Sigma<_c)
  *   diag_G, diag_Gless   complex [nE][Ny][Nx]
  *   bond_G, bond_Gless   complex [nE][nbonds]  (G_ij and G<_ij, i first node)
@@ -40,6 +43,12 @@
  * valid once that stream has been synchronised.  A plan owns its device
  * workspace and tree maps (allocated on first use on a device); calls that
  * share a plan must be serialised by the caller (one stream at a time).
+ * Graph capture: find_solve enqueues kernels and event waits only, so it may
+ * be captured into a HIP graph, provided an eager find_solve of at least as
+ * many energies ran first on the same device (nothing is allocated under
+ * capture; otherwise FIND_E_ARG).  Buffers a captured solve references stay
+ * valid until find_plan_destroy: a later eager solve that needs larger
+ * buffers allocates new ones and keeps the old.
  * No function throws across this boundary; errors are returned as
  * find_status and described by find_last_error() (thread-local string).
  */
@@ -59,7 +68,7 @@ typedef enum {
   FIND_OK = 0,
   FIND_E_ARG = 1,         /* invalid argument (sizes, NULL pointers, stencil) */
   FIND_E_NOMEM = 2,       /* device allocation failed / over budget            */
-  FIND_E_SINGULAR = 3,    /* exactly zero pivot met (see find_sync_status)      */
+  FIND_E_SINGULAR = 3,    /* zero or tiny pivot met (see find_sync_status)      */
   FIND_E_DEVICE = 4,      /* HIP runtime error                                  */
   FIND_E_UNSUPPORTED = 5  /* shape beyond what the kernels support             */
 } find_status;
@@ -95,17 +104,19 @@ typedef enum { FIND_CPLX_4M = 0, FIND_CPLX_3M = 1 } find_complex_mode;
  *                 multiply-add either way.
  *   symmetric     1 asserts that A is complex symmetric (H real symmetric,
  *                 Sigma_L and Sigma_R complex symmetric, as for leads with a
- *                 real transverse basis) and Sigma< anti-Hermitian.  Every
- *                 Schur complement U is then complex symmetric (Prop. 1 of
- *                 the paper) and every R anti-Hermitian, so only their lower
- *                 triangles are formed and the upper triangles are mirrored
- *                 (s b^2 fewer complex multiply-adds per elimination; the
- *                 flop model of find_plan_flops follows).  In the mixed
- *                 forms only U is halved: R is formed whole, because the FP32
- *                 rounding of its products is not anti-Hermitian and
- *                 mirroring one triangle amplifies it near resonances.
- *                 Inputs that break the assertion give wrong results.
- *                 0 (default) = general.
+ *                 real transverse basis).  Every Schur complement U is then
+ *                 complex symmetric (Prop. 1 of the paper), so only its lower
+ *                 triangle is formed and readers take the upper entries from
+ *                 their mirrors (s b^2 / 2 fewer complex multiply-adds per
+ *                 elimination; the flop model of find_plan_flops follows).
+ *                 R (anti-Hermitian when Sigma< is) is formed whole: the two
+ *                 computed triangles round differently, and mirroring one of
+ *                 them amplifies the rounding of G< by orders of magnitude at
+ *                 energies near resonances.  The mirrored U itself costs a
+ *                 factor of a few in accuracy at ill-conditioned energies
+ *                 (errors up to ~5e-10 where the general form has 1e-10), so
+ *                 the general form is the accurate default.  Inputs that break
+ *                 the assertion give wrong results.  0 (default) = general.
  *   streams       energy groups solved concurrently inside one pass (0 or 1
  *                 = one, on the caller's stream; 2..4 = that many groups, each
  *                 on a stream of the plan, forked from and joined back to the
@@ -145,15 +156,23 @@ find_status find_plan_create(int Nx, int Ny, int stencil, const find_plan_opts* 
 find_status find_plan_destroy(find_plan plan);
 
 /* Device bytes one find_solve over nE energies holds (plan maps + energy
- * pool + elimination workspace); for serving admission.  want_bonds selects
- * the leaf extraction that also yields the bond entries. */
+ * pool + elimination workspace), sized as find_solve sizes them on the
+ * current device (its CU count; 256 CUs if no device is present); for
+ * serving admission.  The pool holds, per energy, the U and R blocks of
+ * every cluster (the storage of eq. (major-update) and eq.
+ * (gless-update-rule)); buffers only grow, so a plan that ran a larger solve
+ * holds more.  want_bonds selects the leaf extraction that also yields the
+ * bond entries. */
 find_status find_plan_footprint(find_plan plan, int nE, int want_bonds, size_t* bytes);
 
 /* Algorithmic real flops per energy (8 per complex multiply-add): for each
  * elimination with s eliminated and b kept nodes, s^3/3 + 2 s^2 b + 3 s b^2
- * complex multiply-adds (LU of A(S,S), L = A(B,S) A(S,S)^-1, the Schur update
- * of eq. (major-update) and the two products of eq. (gless-update-rule)
- * arranged as W = [-L, I] Sigma, R = W [-L, I]^dagger); plus 2 b'^3 for each
+ * complex multiply-adds (the paper's operation counts, eq.
+ * (basic-computation-cost) for U: LU of A(S,S), L = A(B,S) A(S,S)^-1, the
+ * Schur update of eq. (major-update); eq. (gless-computation-cost) for R: the
+ * two products of eq. (gless-update-rule) arranged as W = [-L, I] Sigma,
+ * R = W [-L, I]^dagger), reduced by the exact zeros and the halved
+ * triangles of the plan's form; plus 2 b'^3 for each
  * final leaf block of size b' (the inverse G and T = R G^dagger; the requested
  * entries of G< = G T are O(b') dot products each). */
 find_status find_plan_flops(find_plan plan, int want_bonds, double* flops_per_energy);
@@ -189,8 +208,12 @@ find_status find_solve_scattering(find_plan plan, int nE, const double* energies
                                   double* bond_G, double* bond_Gless, double* bond_J, void* hip_stream);
 
 /* Wait for `hip_stream`, then report FIND_E_SINGULAR if the last solve on
- * this plan met an exactly-zero pivot (the energy index is in
- * find_last_error()), else FIND_OK. */
+ * this plan met a zero or tiny pivot in the LU of some A(S,S) (eq.
+ * (express-L)) or of a final leaf block (eq. (cd1)): |re| + |im| of the pivot
+ * below 1e3 * eps * the largest |re| + |im| of that block (eps = 2^-52).  A
+ * zero pivot is replaced by 1 so that the solve stays finite; a tiny one is
+ * used as it is; the results of that energy are unreliable either way.  The
+ * first such energy index is in find_last_error().  Else FIND_OK. */
 find_status find_sync_status(find_plan plan, void* hip_stream);
 
 /* Thread-local description of the last error of this thread. */

@@ -70,6 +70,10 @@ struct DevState {
   std::vector<hipStream_t> lane_st;
   std::vector<hipEvent_t> lane_ev;
   hipEvent_t fork_ev = nullptr;
+  // a solve on this device was captured into a graph: buffers the graph
+  // references are retired (kept until the plan is destroyed) instead of freed
+  bool captured = false;
+  std::vector<void*> retired;
 };
 
 __global__ void k_fill_int(int* p, int n, int v) {
@@ -115,6 +119,7 @@ struct find_plan_s {
   std::map<int, std::unique_ptr<DevState>> dev;
   int last_nE = 0;
   int last_device = -1;
+  int* last_status = nullptr;  // device pivot-status array of the last solve (last_nE entries)
   bool profiling = false;
   std::vector<int> tiles;      // wave-tile configuration per stage
   std::vector<int> tile_mask;  // bit mask of the configurations each stage has
@@ -134,6 +139,7 @@ void free_dev(DevState& d) {
                   d.d_outnode, d.d_outbond, d.pool, d.ws, d.status};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
+  for (void* p : d.retired) (void)hipFree(p);
   if (cur >= 0) (void)hipSetDevice(cur);
 }
 
@@ -146,19 +152,26 @@ find_status upload(T** dptr, const std::vector<T>& h, size_t& bytes) {
   return FIND_OK;
 }
 
-// Halved triangles of the symmetric form: bit 0 = U (complex symmetric), bit
-// 1 = R (anti-Hermitian).  The mixed forms form R whole: the FP32 rounding of
-// its products is not anti-Hermitian, and mirroring one triangle amplifies it
-// at energies near resonances of the device.
-int sym_bits(const find_plan_opts& o) {
-  if (!o.symmetric) return 0;
-  return o.precision == FIND_PREC_FP64 ? 3 : 1;
-}
+// Halved triangle of the symmetric form: bit 0 = U (complex symmetric, Prop. 1
+// of the paper).  R, although anti-Hermitian, is formed whole: the rounding of
+// its two computed triangles differs, and replacing one by the mirror of the
+// other amplifies the rounding of G< = G R G^dagger by orders of magnitude at
+// energies near resonances of the device (where G is large).
+int sym_bits(const find_plan_opts& o) { return o.symmetric ? 1 : 0; }
 
 // Workspace (complex elements) of one Schur elimination: the tall block
 // [A(S,S); A(B,S)] (n x s), L (b x s) and W_q (b x ssig).
 long long elim_ws(const Elim& e) {
   return (long long)e.n * e.s + (long long)e.b * e.s + (long long)e.b * e.ssig;
+}
+
+// Workgroup slots of a device: workgroups resident per CU (the kernels are
+// compiled for occupancy 3; FIND_SLOTS_PER_CU overrides, 1..16) times its
+// CUs.  cus < 1 (no device to ask) counts the 256 CUs of an MI355X.
+int slots_for(int cus) {
+  int per_cu = 3;
+  if (const char* env = getenv("FIND_SLOTS_PER_CU")) per_cu = std::max(1, std::min(16, atoi(env)));
+  return std::max(1, per_cu * (cus > 0 ? cus : 256));
 }
 
 find_status ensure_device(find_plan_s* p, DevState** out) {
@@ -170,9 +183,7 @@ find_status ensure_device(find_plan_s* p, DevState** out) {
   ds->device = dev;
   int cus = 0;
   HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  int per_cu = 3;  // workgroups resident per CU (the kernel is compiled for occupancy 3)
-  if (const char* env = getenv("FIND_SLOTS_PER_CU")) per_cu = std::max(1, std::min(16, atoi(env)));
-  ds->slots = std::max(1, per_cu * cus);
+  ds->slots = slots_for(cus);
   const Plan& P = p->P;
   // elimination records, sorted by decreasing cost inside each stage
   std::vector<ElimDev> he(P.elims.size());
@@ -293,6 +304,29 @@ int chunk_energies(const find_plan_s* p, const DevState& d, int nE) {
 
 }  // namespace
 
+// Stage sizes (workspace stride, largest front) and slots of the current
+// device (256 CUs if no device is present), as ensure_device sets them,
+// without touching device memory.
+static void host_stages(const find_plan_s* p, DevState* d) {
+  const Plan& P = p->P;
+  int dev = -1, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    cus = 0;
+  }
+  d->slots = slots_for(cus);
+  for (const Stage& st : P.stages) {
+    DevStage ds{st.first, st.count, st.phase, st.variant, 0.0, 1, 0, 0, 1, nullptr};
+    for (int k = st.first; k < st.first + st.count; ++k) {
+      const Elim& e = P.elims[k];
+      ds.ws_stride = std::max<long long>(ds.ws_stride, e.kind == K_FINAL ? 3LL * e.b * e.b : elim_ws(e));
+      ds.maxn = std::max(ds.maxn, e.n);
+    }
+    d->stages.push_back(ds);
+  }
+}
+
 extern "C" {
 
 const char* find_last_error(void) { return g_err.c_str(); }
@@ -407,7 +441,7 @@ find_status find_plan_export(find_plan plan, int32_t* elims, int32_t* maps, int3
 find_status find_plan_flops(find_plan plan, int want_bonds, double* flops_per_energy) {
   if (!plan || !flops_per_energy) return fail(FIND_E_ARG, "find_plan_flops: NULL argument");
   const int sb = sym_bits(plan->opts);
-  *flops_per_energy = plan->P.flops[sb == 0 ? 0 : sb == 3 ? 1 : 2][want_bonds ? 1 : 0];
+  *flops_per_energy = plan->P.flops[sb][want_bonds ? 1 : 0];
   return FIND_OK;
 }
 
@@ -415,18 +449,10 @@ find_status find_plan_footprint(find_plan plan, int nE, int want_bonds, size_t* 
   (void)want_bonds;
   if (!plan || !bytes || nE < 1) return fail(FIND_E_ARG, "find_plan_footprint: bad argument");
   const Plan& P = plan->P;
-  // the same sizing find_solve uses, for 3 workgroups on each of 256 CUs
+  // the same sizing find_solve uses, for the current device's slots (if a
+  // device is present; else those of an MI355X)
   DevState d;
-  d.slots = 3 * 256;
-  for (const Stage& st : P.stages) {
-    DevStage ds{st.first, st.count, st.phase, st.variant, 0.0, 1, 0, 0, 1, nullptr};
-    for (int k = st.first; k < st.first + st.count; ++k) {
-      const Elim& e = P.elims[k];
-      ds.ws_stride = std::max<long long>(ds.ws_stride, e.kind == K_FINAL ? 3LL * e.b * e.b : elim_ws(e));
-      ds.maxn = std::max(ds.maxn, e.n);
-    }
-    d.stages.push_back(ds);
-  }
+  host_stages(plan, &d);
   d.maps_bytes = (P.map_node.size() * 2 + P.elims.size() * sizeof(ElimDev) / 4 + P.outbonds.size() * 5 +
                   P.outnode_node.size() * 2) * 4;
   int ec = chunk_energies(plan, d, nE);
@@ -440,35 +466,67 @@ find_status find_plan_footprint(find_plan plan, int nE, int want_bonds, size_t* 
 
 namespace {
 
+// Replace a device buffer by a larger one.  Once a solve on this device has
+// been captured, the old buffer is retired (kept until the plan is destroyed)
+// so that replays of the captured graph still address valid memory.
+template <class T>
+find_status regrow(DevState* d, T** buf, size_t* have, size_t need, hipStream_t st, const char* what) {
+  if (*have >= need) return FIND_OK;
+  if (*buf) {
+    HIPCHK(hipStreamSynchronize(st));
+    if (d->captured) d->retired.push_back(*buf);
+    else HIPCHK(hipFree(*buf));
+    *buf = nullptr;
+    *have = 0;
+  }
+  if (hipMalloc(buf, need * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    *buf = nullptr;
+    return fail(FIND_E_NOMEM, std::string("find_solve: ") + what + " allocation failed");
+  }
+  *have = need;
+  return FIND_OK;
+}
+
 // Device buffers for a solve of nE energies (grown on demand); *ec = energies per pass.
+// Under stream capture nothing may be allocated: the plan's device state and
+// buffers must already be large enough (an eager solve of at least as many
+// energies on this device and stream configuration), else FIND_E_ARG.
 find_status prepare(find_plan_s* plan, int nE, hipStream_t st, DevState** dout, int* ec) {
   const Plan& P = plan->P;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIPCHK(hipStreamIsCapturing(st, &cs));
+  const bool capturing = cs != hipStreamCaptureStatusNone;
   DevState* d = nullptr;
-  find_status fs = ensure_device(plan, &d);
-  if (fs != FIND_OK) return fs;
+  if (capturing) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    auto it = plan->dev.find(dev);
+    if (it == plan->dev.end())
+      return fail(FIND_E_ARG, "find_solve: captured before an eager solve set the plan up on this device");
+    d = it->second.get();
+  } else {
+    find_status fs = ensure_device(plan, &d);
+    if (fs != FIND_OK) return fs;
+  }
   *ec = chunk_energies(plan, *d, nE);
   if (*ec < 1) return fail(FIND_E_NOMEM, "find_solve: workspace budget too small for one energy");
   const size_t ws_need = ws_total(*d, *ec, lanes_of(plan));
-  if (d->ws_elems < ws_need) {
-    if (d->ws) { HIPCHK(hipStreamSynchronize(st)); HIPCHK(hipFree(d->ws)); d->ws = nullptr; d->ws_elems = 0; }
-    if (hipMalloc(&d->ws, ws_need * sizeof(double2)) != hipSuccess)
-      return fail(FIND_E_NOMEM, "find_solve: workspace allocation failed");
-    d->ws_elems = ws_need;
-  }
   const size_t pool_need = size_t(*ec) * size_t(P.pool_per_energy);
-  if (d->pool_elems < pool_need) {
-    if (d->pool) { HIPCHK(hipStreamSynchronize(st)); HIPCHK(hipFree(d->pool)); d->pool = nullptr; d->pool_elems = 0; }
-    if (hipMalloc(&d->pool, pool_need * sizeof(double2)) != hipSuccess)
-      return fail(FIND_E_NOMEM, "find_solve: energy pool allocation failed");
-    d->pool_elems = pool_need;
-  }
-  if (d->status_len < size_t(nE)) {
-    if (d->status) { HIPCHK(hipStreamSynchronize(st)); HIPCHK(hipFree(d->status)); d->status = nullptr; d->status_len = 0; }
-    if (hipMalloc(&d->status, size_t(nE) * sizeof(int)) != hipSuccess)
-      return fail(FIND_E_NOMEM, "find_solve: status allocation failed");
-    d->status_len = nE;
-  }
   const int lanes = lanes_of(plan);
+  if (capturing) {
+    if (d->ws_elems < ws_need || d->pool_elems < pool_need || d->status_len < size_t(nE) ||
+        (lanes > 1 && (int(d->lane_st.size()) < lanes || !d->fork_ev)))
+      return fail(FIND_E_ARG, "find_solve: a captured solve needs buffers that an eager solve of at least as "
+                              "many energies has allocated (nothing is allocated under capture)");
+    d->captured = true;
+    *dout = d;
+    return FIND_OK;
+  }
+  find_status fs;
+  if ((fs = regrow(d, &d->ws, &d->ws_elems, ws_need, st, "workspace")) != FIND_OK) return fs;
+  if ((fs = regrow(d, &d->pool, &d->pool_elems, pool_need, st, "energy pool")) != FIND_OK) return fs;
+  if ((fs = regrow(d, &d->status, &d->status_len, size_t(nE), st, "status")) != FIND_OK) return fs;
   while (int(d->lane_st.size()) < lanes && lanes > 1) {
     hipStream_t s2;
     hipEvent_t e2;
@@ -531,24 +589,30 @@ hipError_t launch_stage_k(const find_plan_s* plan, const DevState* d, int k, Sta
   return launch_stage(a, s2.maxn, tc, plan->opts.complex_mode, grid, st);
 }
 
-// The solve of find_solve and find_solve_scattering (sigma_d and sigma_less_d
-// NULL for the former); arguments checked by the callers.
-find_status solve_impl(find_plan plan, int nE, const double* energies, const double* H, const double* sigma,
-                       const double* sigma_less, const double* sigma_d, const double* sigma_less_d,
-                       double* diag_G, double* diag_Gless,
-                       double* bond_G, double* bond_Gless, double* bond_J, void* hip_stream) {
-  std::lock_guard<std::mutex> lk(plan->mu);
-  hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  DevState* d = nullptr;
-  int ec = 0;
-  find_status fs = prepare(plan, nE, st, &d, &ec);
-  if (fs != FIND_OK) return fs;
+// Device buffers a solve runs in: the energy pool (ec energies), the
+// elimination workspace (lanes groups of lane_ws elements) and the per-energy
+// pivot status (nE entries).
+struct SolveBufs {
+  double2* pool;
+  double2* ws;
+  int* status;
+  int ec;
+  int lanes;
+  size_t lane_ws;
+  bool profiling;
+};
+
+// Enqueue every pass of a solve into `b` on `st`; arguments checked by the callers.
+find_status enqueue_solve(find_plan plan, DevState* d, const SolveBufs& b, int nE, const double* energies,
+                          const double* H, const double* sigma, const double* sigma_less, const double* sigma_d,
+                          const double* sigma_less_d, double* diag_G, double* diag_Gless, double* bond_G,
+                          double* bond_Gless, double* bond_J, hipStream_t st) {
   const int variant = (bond_G || bond_Gless || bond_J) ? 1 : 0;
-  if (plan->profiling) d->ev_used = 0;  // the profile describes this solve
-  hipLaunchKernelGGL(k_fill_int, dim3((nE + 255) / 256), dim3(256), 0, st, d->status, nE, 0);
+  if (b.profiling) d->ev_used = 0;  // the profile describes this solve
+  hipLaunchKernelGGL(k_fill_int, dim3((nE + 255) / 256), dim3(256), 0, st, b.status, nE, 0);
   HIPCHK(hipGetLastError());
-  const int lanes = lanes_of(plan);
-  const size_t lws = lane_ws(*d, ec, lanes);
+  const int ec = b.ec, lanes = b.lanes;
+  const size_t lws = b.lane_ws;
   for (int e0 = 0; e0 < nE; e0 += ec) {
     const int ne = std::min(ec, nE - e0);
     // energy groups of this pass: one on the caller's stream, or `lanes`
@@ -556,7 +620,7 @@ find_status solve_impl(find_plan plan, int nE, const double* energies, const dou
     const int ng = (lanes > 1 && ne > 1) ? std::min(lanes, ne) : 1;
     const int per = (ne + ng - 1) / ng;
     if (ng > 1) {
-      if (plan->profiling) {   // one event pair around the whole pass
+      if (b.profiling) {   // one event pair around the whole pass
         while (d->ev.size() < 2 * (d->ev_used + 1)) {
           hipEvent_t ev;
           HIPCHK(hipEventCreate(&ev));
@@ -580,8 +644,9 @@ find_status solve_impl(find_plan plan, int nE, const double* energies, const dou
       OutArgs o;
       pass_args(plan, d, variant, g0, gn, energies, H, sigma, sigma_less, diag_G, diag_Gless, bond_G, bond_Gless,
                 bond_J, &a, &o, sigma_d, sigma_less_d);
-      a.ws = d->ws + size_t(g) * lws;
-      a.pool = d->pool + size_t(g0 - e0) * size_t(plan->P.pool_per_energy);   // kernels index energies from 0
+      a.ws = b.ws + size_t(g) * lws;
+      a.pool = b.pool + size_t(g0 - e0) * size_t(plan->P.pool_per_energy);   // kernels index energies from 0
+      a.status = b.status + g0;
       {
         const hipError_t he = launch_onsite(a, sg);
         if (he != hipSuccess) return fail(FIND_E_DEVICE, std::string("onsite launch: ") + hipGetErrorString(he));
@@ -590,7 +655,7 @@ find_status solve_impl(find_plan plan, int nE, const double* energies, const dou
         const DevStage& s2 = d->stages[k];
         if (s2.variant >= 0 && s2.variant != variant) continue;
         if ((long long)s2.count * gn < 1) continue;
-        const bool prof = plan->profiling && ng == 1;
+        const bool prof = b.profiling && ng == 1;
         if (prof) {
           while (d->ev.size() < 2 * (d->ev_used + 1)) {
             hipEvent_t ev;
@@ -613,14 +678,35 @@ find_status solve_impl(find_plan plan, int nE, const double* energies, const dou
         HIPCHK(hipStreamWaitEvent(st, d->lane_ev[g], 0));
       }
     }
-    if (ng > 1 && plan->profiling) {
+    if (ng > 1 && b.profiling) {
       HIPCHK(hipEventRecord(d->ev[2 * d->ev_used + 1], st));
       ++d->ev_used;
     }
   }
   plan->last_nE = nE;
   plan->last_device = d->device;
+  plan->last_status = b.status;
   return FIND_OK;
+}
+
+// The solve of find_solve and find_solve_scattering (sigma_d and sigma_less_d
+// NULL for the former) in the plan's own buffers; arguments checked by the callers.
+find_status solve_impl(find_plan plan, int nE, const double* energies, const double* H, const double* sigma,
+                       const double* sigma_less, const double* sigma_d, const double* sigma_less_d,
+                       double* diag_G, double* diag_Gless,
+                       double* bond_G, double* bond_Gless, double* bond_J, void* hip_stream) {
+  std::lock_guard<std::mutex> lk(plan->mu);
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  plan->last_status = nullptr;
+  plan->last_nE = 0;
+  DevState* d = nullptr;
+  int ec = 0;
+  find_status fs = prepare(plan, nE, st, &d, &ec);
+  if (fs != FIND_OK) return fs;
+  const int lanes = lanes_of(plan);
+  const SolveBufs b{d->pool, d->ws, d->status, ec, lanes, lane_ws(*d, ec, lanes), plan->profiling};
+  return enqueue_solve(plan, d, b, nE, energies, H, sigma, sigma_less, sigma_d, sigma_less_d, diag_G, diag_Gless,
+                       bond_G, bond_Gless, bond_J, st);
 }
 
 }  // namespace
@@ -719,6 +805,7 @@ find_status find_plan_autotune(find_plan plan, int nE, const double* energies, c
   HIPCHK(hipStreamSynchronize(st));
   plan->last_nE = ne;
   plan->last_device = d->device;
+  plan->last_status = d->status;
   return FIND_OK;
 }
 
@@ -780,14 +867,13 @@ find_status find_sync_status(find_plan plan, void* hip_stream) {
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   HIPCHK(hipStreamSynchronize(st));
   std::lock_guard<std::mutex> lk(plan->mu);
-  auto it = plan->dev.find(plan->last_device);
-  if (it == plan->dev.end() || plan->last_nE == 0) return FIND_OK;
+  if (!plan->last_status || plan->last_nE == 0) return FIND_OK;
   std::vector<int> h(plan->last_nE);
-  HIPCHK(hipMemcpy(h.data(), it->second->status, h.size() * sizeof(int), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(h.data(), plan->last_status, h.size() * sizeof(int), hipMemcpyDeviceToHost));
   for (size_t e = 0; e < h.size(); ++e)
     if (h[e]) {
       char buf[96];
-      snprintf(buf, sizeof buf, "zero pivot met at energy index %zu", e);
+      snprintf(buf, sizeof buf, "zero or tiny pivot (|pivot| < 1e3 eps max|A(S,S)|) met at energy index %zu", e);
       return fail(FIND_E_SINGULAR, buf);
     }
   return FIND_OK;

@@ -128,6 +128,7 @@ struct LdsT {
   double2 candrow[2][kW][16];
   double2 tri[16 * 16];
   double2 tinv[16 * 16];
+  unsigned long long red[kW];   // per-wave partial maxima (norm of the pivot block)
   typename std::conditional<(NT == 256 && MAXN <= 512), WgLds, NoWgLds>::type wg;
 };
 template <class LDS>
@@ -144,7 +145,7 @@ struct Front {
   const double2* U1;
   int ld0, ld1;
   Orig o;
-  int sym;             // sources hold only the lower triangle of U (= U^T) (bit 0) and of R (= -R^dagger) (bit 1)
+  int sym;             // bit 0: sources hold only the lower triangle of U (= U^T)
 
   __device__ double2 a(int r, int c) const {
     const int spr = srcpos[r], spc = srcpos[c];
@@ -166,7 +167,6 @@ struct Front {
       const int ld = sr ? ld1 : ld0;
       const double2* R = (sr ? U1 : U0) + (size_t)ld * ld;
       const int pr = spr & 0xffffff, pc = spc & 0xffffff;
-      if ((sym & 2) && pr < pc) { const double2 v = R[(size_t)pr * ld + pc]; return make_double2(-v.x, v.y); }
       return R[(size_t)pc * ld + pr];
     }
     const int gr = node[r], gc = node[c];
@@ -501,6 +501,23 @@ __device__ __forceinline__ u64 wave_max(u64 x) {
   return umax64(umax64(readlane_u64(x, 0), readlane_u64(x, 16)), umax64(readlane_u64(x, 32), readlane_u64(x, 48)));
 }
 
+// Pivot threshold of a front: kPivotRel * eps * ||A(S,S)||, with the norm
+// taken as the largest |re| + |im| over the block (the measure the pivot
+// search compares).  Each thread passes the maximum over the entries it
+// assembled; the workgroup maximum is formed here.  Called by every thread;
+// it ends with the barrier that publishes the assembled block.
+constexpr double kPivotRel = 1e3;
+template <class LDS>
+__device__ __forceinline__ double pivot_threshold(LDS& L, double part) {
+  const u64 w = wave_max((u64)__double_as_longlong(part));   // non-negative doubles order as integers
+  if ((threadIdx.x & 63) == 0) L.red[threadIdx.x >> 6] = w;
+  __syncthreads();
+  u64 m = L.red[0];
+#pragma unroll
+  for (int k = 1; k < LDS::kW; ++k) m = umax64(m, L.red[k]);
+  return kPivotRel * 2.220446049250313e-16 * __longlong_as_double((long long)m);
+}
+
 // Sum over the wave, returned to every lane (same pattern as wave_max).
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double x) {
@@ -527,9 +544,11 @@ __device__ __forceinline__ int prow(const int* pm, int s, int r) { return r < s 
 // block, panels of NB columns are brought up to date left-looking from the
 // block's earlier panels, factored in registers (rows spread over the
 // threads), and their U rows formed; the rest of the matrix gets one
-// MFMA trailing update per outer block.  Returns true if a zero pivot was met.
+// MFMA trailing update per outer block.  Returns true if a pivot was zero or
+// below thr in magnitude (|re| + |im|); a zero pivot is replaced by 1 so that
+// the factorization stays finite, a tiny one is kept.
 template <int RPT, int NB, bool WG, class LDS>
-__device__ __forceinline__ bool tall_lu(LDS& L, double2* FA, int n, int s) {
+__device__ __forceinline__ bool tall_lu(LDS& L, double2* FA, int n, int s, double thr) {
   constexpr int NT = LDS::kNT;
   constexpr int NB2 = 32;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -601,6 +620,8 @@ __device__ __forceinline__ bool tall_lu(LDS& L, double2* FA, int n, int s) {
           int piv = kKeyRows - 1 - int(gk & (kKeyRows - 1));
           bool pvv = (gk >> kKeyBits) != 0;            // non-zero pivot magnitude
           if (piv < j || piv >= ms) { piv = j; pvv = false; }   // (logical row j is always eligible)
+          // magnitude of the pivot (the key's bits above the row field)
+          if (__longlong_as_double((long long)(gk & ~(u64)(kKeyRows - 1))) < thr) singular = true;
           if (tid == 0 && piv != j) {  // relabel: logical rows k0+j and k0+piv trade physical rows
             const int t = pm[k0 + j]; pm[k0 + j] = pm[k0 + piv]; pm[k0 + piv] = t;
           }
@@ -739,11 +760,16 @@ __global__ __launch_bounds__(NT, (TC == kTileWg || NT == 512) ? 2 : 3) void k_st
                         pool + a.onsite_off, a.Nx, a.Ny, a.nst, a.sscat != nullptr}, a.sym};
     // 1. assemble the tall block [A_g(S,S); A_g(B,S)]; the other blocks of A_g
     //    and all of Sigma_g are gathered from their sources by the products
-    for_each_rc<NT>(na, s, [&](int r, int c) { FA[(size_t)c * na + r] = fr.a(r, c); });
-    __syncthreads();
+    double amax = 0.0;   // this thread's largest |re| + |im| in A_g(S,S)
+    for_each_rc<NT>(na, s, [&](int r, int c) {
+      const double2 v = fr.a(r, c);
+      FA[(size_t)c * na + r] = v;
+      if (r < s) amax = fmax(amax, fabs(v.x) + fabs(v.y));
+    });
+    const double thr = pivot_threshold(L, amax);
     // 2. tall LU, 3. L = L21 L11^{-1}
     if (s > 0) {
-      if (tall_lu<RPT, NB, TC == kTileWg>(L, FA, na, s) && tid == 0) a.status[e] = 1;
+      if (tall_lu<RPT, NB, TC == kTileWg>(L, FA, na, s, thr) && tid == 0) a.status[e] = 1;
       trsm_right_unit_lower(L, FA, Lo, na, s, ba);
     }
     // 4. U = A(B,B) - L A(S,B); 5. W_q and R (FP32 products in the mixed form,
@@ -763,10 +789,10 @@ __global__ __launch_bounds__(NT, (TC == kTileWg || NT == 512) ? 2 : 3) void k_st
     auto br = [=](int k, int c) { return k < q0 ? fr.s(k, s + c) : conjd(Lo[(size_t)(k - q0) * ba + c]); };
     auto cr = [=](int r, int c) { return fr.s(s + r, s + c); };
     auto sr = [=](int r, int c, double2 v) { Ro[(size_t)c * b + r] = v; };
-    // with a.sym, U is complex symmetric and R anti-Hermitian: their tiles
-    // above the diagonal are not formed, and every reader of U and R takes
-    // an upper entry from its mirror below the diagonal
-    const int tri = (a.sym & 1) ? ba : 0, trir = (a.sym & 2) ? ba : 0;
+    // with a.sym, U is complex symmetric: its tiles above the diagonal are not
+    // formed, and every reader of U takes an upper entry from its mirror below
+    // the diagonal (R is formed whole)
+    const int tri = (a.sym & 1) ? ba : 0;
     auto products = [&](auto fu, auto fs) {
       constexpr bool FU = decltype(fu)::value, FS = decltype(fs)::value;
       gemm_schur<NT, FU, TC, CM == 1>(L, ba, ba, s, tri, lo_, bu, cu, su);
@@ -776,7 +802,7 @@ __global__ __launch_bounds__(NT, (TC == kTileWg || NT == 512) ? 2 : 3) void k_st
       } else {
         if (q > 0) gemm_schur<NT, FS, TC, CM == 1>(L, ba, q, q, 0, lo_, bw, cw, sw);
         __syncthreads();
-        gemm_schur<NT, FS, TC, CM == 1>(L, ba, ba, q0 + q, trir, ar, br, cr, sr);
+        gemm_schur<NT, FS, TC, CM == 1>(L, ba, ba, q0 + q, 0, ar, br, cr, sr);
       }
     };
     // rows and columns of the kept nodes not coupled to S: U and R keep the
@@ -821,22 +847,22 @@ __global__ __launch_bounds__(NT, 3) void k_final(StageArgs a, OutArgs o) {
     const double2* Rin = Uin + (size_t)bp * bp;   // R_K
     double2* G = pool + E.dst;                    // G(K,K), bp x bp
     for (int k = tid; k < bp; k += NT) L.perm[k] = k;
+    double amax = 0.0;   // this thread's largest |re| + |im| in U_K
     for_each_rc<NT>(n, bp, [&](int r, int c) {
-      FA[(size_t)c * n + r] = r < bp ? Uin[(a.sym & 1) && r < c ? (size_t)r * bp + c : (size_t)c * bp + r]
-                                     : make_double2(r - bp == c ? 1.0 : 0.0, 0.0);
+      const double2 v = r < bp ? Uin[(a.sym & 1) && r < c ? (size_t)r * bp + c : (size_t)c * bp + r]
+                               : make_double2(r - bp == c ? 1.0 : 0.0, 0.0);
+      FA[(size_t)c * n + r] = v;
+      if (r < bp) amax = fmax(amax, fabs(v.x) + fabs(v.y));
     });
-    __syncthreads();
-    if (tall_lu<RPT, NB, false>(L, FA, n, bp) && tid == 0) a.status[e] = 1;
+    const double thr = pivot_threshold(L, amax);
+    if (tall_lu<RPT, NB, false>(L, FA, n, bp, thr) && tid == 0) a.status[e] = 1;
     // G(:, perm[k]) = L(:, k): the L solve of the identity rows stores U_K^{-1}
     trsm_right_unit_lower(L, FA, G, n, bp, bp);
     // T = R_K G^dagger   (gemm_sub returns 0 - R G^dagger); R_K vanishes outside
     // its first rs rows and columns, so T has rs rows and the sum runs over rs
-    const int symr = a.sym & 2, rs = E.ssig;
+    const int rs = E.ssig;
     gemm_sub<NT>(rs, bp, rs,
-             [=](int r, int k) {
-               if (symr && r < k) { const double2 v = Rin[(size_t)r * bp + k]; return make_double2(-v.x, v.y); }
-               return Rin[(size_t)k * bp + r];
-             },
+             [=](int r, int k) { return Rin[(size_t)k * bp + r]; },
              [=](int k, int c) { return conjd(G[(size_t)k * bp + c]); },
              [=](int r, int c) { return zero2(); },
              [=](int r, int c, double2 v) { T[(size_t)c * bp + r] = make_double2(-v.x, -v.y); });

@@ -40,8 +40,8 @@ struct StageArgs {
   double2* ws;            // per-slot workspace
   long long ws_stride;
   int Nx, Ny, nst;
-  int* status;            // per energy of this pass: 1 = zero pivot met
-  int sym;                // bit 0: U complex symmetric (half formed), bit 1: R anti-Hermitian (half formed)
+  int* status;            // per energy of this pass: 1 = zero or tiny pivot met
+  int sym;                // bit 0: U complex symmetric (lower half formed); R is always formed whole
 };
 
 struct OutArgs {

@@ -52,15 +52,15 @@ double elim_flops(const Elim& e, int sym) {
   // the kept ones): W_q = Sigma(B,S_q) - L_q Sigma(S_q,S_q) costs b q^2 and
   // R = Sigma(B,B) - [L_q | W_q] [Sigma(S_q,B) ; L_q^dagger] costs 2 q b^2 (q b^2
   // when no kept node carries Sigma<, so that Sigma(S_q,B) = 0).  With U complex
-  // symmetric (sym bit 0) and R anti-Hermitian (bit 1) only half of U, of R, is
-  // formed.  With R = 0 (no Sigma< in the front) W and R are not formed.
+  // symmetric (sym bit 0) only its lower half is formed; R is always formed
+  // whole.  With R = 0 (no Sigma< in the front) W and R are not formed.
   // Kept nodes not coupled to S (b - bact of them) take no part in any of it.
   b = e.bact;
-  const double hu = (sym & 1) ? 0.5 : 1.0, hr = (sym & 2) ? 0.5 : 1.0;
+  const double hu = (sym & 1) ? 0.5 : 1.0;
   const double base = s * s * s / 3.0 + s * s * b + hu * s * b * b;
   if (e.rzero) return 8.0 * base;
   const double q0 = e.bsig ? q : 0.0;
-  return 8.0 * (base + b * q * q + hr * b * b * (q0 + q));
+  return 8.0 * (base + b * q * q + b * b * (q0 + q));
 }
 
 namespace {
@@ -436,9 +436,8 @@ struct Builder {
       for (int k = st.first; k < st.first + st.count; ++k) {
         const Elim& e = P.elims[k];
         P.max_n = std::max(P.max_n, e.n); P.max_s = std::max(P.max_s, e.s); P.max_b = std::max(P.max_b, e.b);
-        for (int mode = 0; mode < 3; ++mode) {
-          const int sym = mode == 0 ? 0 : mode == 1 ? 3 : 1;
-          const double f = elim_flops(e, sym);
+        for (int mode = 0; mode < 2; ++mode) {
+          const double f = elim_flops(e, mode);   // 0: general, 1: U halved (symmetric form)
           if (st.variant < 0) { P.flops[mode][0] += f; P.flops[mode][1] += f; }
           else P.flops[mode][st.variant] += f;
         }

@@ -72,7 +72,7 @@ struct Plan {
   int max_n = 0, max_s = 0, max_b = 0;
   int n_bonds = 0;
   // per energy: [halved triangles: 0 none, 1 U and R, 2 U only][variant 0/1]
-  double flops[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+  double flops[2][2] = {{0, 0}, {0, 0}};   // [general, symmetric form][diagonal only, with bonds]
 };
 
 int count_bonds(int Nx, int Ny, int stencil);

@@ -212,6 +212,8 @@ def solve(plan: Plan, energies, H, sigma, sigma_less, diag_G, diag_Gless,
     For a plan created with scattering=True, sigma_d and sigma_less_d complex128
     [nE][Ny][Nx] (diagonal scattering self-energies) are required.
     """
+    if not plan.scattering and (sigma_d is not None or sigma_less_d is not None):
+        raise ValueError("sigma_d / sigma_less_d given for a plan created without scattering=True")
     import torch
     Nx, Ny = plan.Nx, plan.Ny
     nE = int(energies.shape[0])

@@ -132,6 +132,31 @@ def scattering_self_energies(Nx: int, Ny: int, nE: int, gamma: float = 0.05, f: 
     return sd, np.ascontiguousarray(sl)
 
 
+def scattering_self_energies_varied(Nx: int, Ny: int, nE: int, gamma: float = 0.05, shift: float = 0.05,
+                                    seed: int = 0) -> tuple[np.ndarray, np.ndarray]:
+    """Diagonal scattering self-energies that differ per energy and per node
+    (an energy-dependent local self-energy with a level shift):
+    Sigma_d[e][y][x] = s - i g / 2 with s ~ U[-shift, shift] and
+    g ~ U[gamma/2, 3 gamma/2], and Sigma<_d = i f_e g with an occupation
+    f_e ~ U[0, 1] per energy (seeded).  Arrays [nE][Ny][Nx]."""
+    rng = np.random.default_rng(seed)
+    s = rng.uniform(-shift, shift, size=(nE, Ny, Nx))
+    g = rng.uniform(0.5 * gamma, 1.5 * gamma, size=(nE, Ny, Nx))
+    f = rng.uniform(0.0, 1.0, size=(nE, 1, 1))
+    return (s - 0.5j * g).astype(np.complex128), (1j * f * g).astype(np.complex128)
+
+
+def general_contact_perturbation(nE: int, Nx: int, scale: float, seed: int = 0) -> np.ndarray:
+    """A seeded complex perturbation [nE][2][Nx][Nx] with no symmetry
+    (entries (a + i b) * scale, a, b ~ U[-1, 1]); added to the lead
+    self-energies it gives contact blocks that are neither complex symmetric
+    nor Hermitian, and as Sigma< one that is not anti-Hermitian."""
+    rng = np.random.default_rng(seed)
+    re = rng.uniform(-1.0, 1.0, size=(nE, 2, Nx, Nx))
+    im = rng.uniform(-1.0, 1.0, size=(nE, 2, Nx, Nx))
+    return (scale * (re + 1j * im)).astype(np.complex128)
+
+
 def bond_counts(Nx: int, Ny: int, stencil: int) -> list[int]:
     n = [max(Nx - 1, 0) * Ny, Nx * max(Ny - 1, 0)]
     if stencil == 9:

@@ -114,8 +114,11 @@ class GpuExecutor:
         self.keep_outputs = keep_outputs
 
     def footprint(self, req: Request) -> int:
+        """Device bytes of the request: its plan's footprint for nE energies,
+        or what the cached plan already holds if that is more (a plan's
+        buffers only grow), plus its inputs and outputs."""
         plan = self.cache.take(req.key)
-        fp = plan.footprint(req.nE, req.want_bonds)
+        fp = max(plan.footprint(req.nE, req.want_bonds), getattr(plan, "held_bytes", 0))
         self.cache.give(req.key, plan, fp, 0)
         io = req.sigma.nbytes * 2 + req.H.nbytes + req.energies.nbytes + 2 * req.nE * req.Nx * req.Ny * 16
         if req.want_bonds:
@@ -125,6 +128,7 @@ class GpuExecutor:
     def start(self, slot: int, req: Request, footprint: int) -> None:
         torch = self.torch
         plan = self.cache.take(req.key)
+        plan.held_bytes = max(getattr(plan, "held_bytes", 0), plan.footprint(req.nE, req.want_bonds))
         s = self.streams[slot]
         with torch.cuda.stream(s):
             t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).pin_memory().to(self.dev, non_blocking=True)

@@ -9,9 +9,9 @@ import pytest
 
 from oracle import dense, rgf
 from paper_1104_0623_amd import inputs
+from tests.parity import TOL, compare, nrel
 
 pytestmark = pytest.mark.gpu
-TOL = 1e-10
 
 
 def find():
@@ -20,24 +20,6 @@ def find():
         pytest.skip("no GPU")
     from paper_1104_0623_amd import find as f
     return f
-
-
-def nrel(x, ref):
-    x, ref = np.asarray(x), np.asarray(ref)
-    return float(np.max(np.abs(x - ref)) / max(np.max(np.abs(ref)), 1e-300))
-
-
-def compare(out, ref, prob, bonds=True, tol=TOL, label=""):
-    nE = prob["energies"].size
-    for e in range(nE):
-        assert nrel(out["diag_G"][e], ref["diag_G"][e]) <= tol, (label, e, "diag_G")
-        assert nrel(out["diag_Gless"][e], ref["diag_Gless"][e]) <= tol, (label, e, "diag_Gless")
-        if bonds and ref["bond_G"].shape[1]:
-            assert nrel(out["bond_G"][e], ref["bond_G"][e]) <= tol, (label, e, "bond_G")
-            assert nrel(out["bond_Gless"][e], ref["bond_Gless"][e]) <= tol, (label, e, "bond_Gless")
-            hmax = np.max(np.abs(prob["H"][1:]))
-            scale = np.max(np.abs(ref["bond_J"][e])) + hmax * np.max(np.abs(ref["bond_Gless"][e]))
-            assert np.max(np.abs(out["bond_J"][e] - ref["bond_J"][e])) <= tol * scale, (label, e, "bond_J")
 
 
 def test_c1_16x16_against_dense():

@@ -308,3 +308,70 @@ def test_scattering_plan_executor_matches_oracle(Nx, Ny, stencil, leaf):
         na = s_ + ba
         for M in (Ag, Sg):
             assert np.all(M[na:, :s_] == 0) and np.all(M[:s_, na:] == 0), k
+
+
+@pytest.mark.parametrize("Nx,Ny,stencil,leaf", [(12, 20, 5, 3), (9, 16, 9, 4), (16, 16, 5, 8), (7, 13, 5, 3)])
+def test_schur_blocks_independent_of_elimination_order(Nx, Ny, stencil, leaf):
+    """Theorem 1 and its corollaries (Sec. 2.2 and the appendix's final
+    conclusion): the U and R each elimination of the plan produces depend
+    only on which nodes have been eliminated, not on the order.  Every U_g
+    (and R_g) of the tree-ordered, level-by-level executor equals the Schur
+    complement onto B_g taken in one step from the original A (and Sigma<)
+    over all nodes eliminated below it, for the upward clusters, the
+    complement clusters and the leaf extraction fronts alike."""
+    from tests.plan_exec import execute
+    find = findlib()
+    E = 0.29 + 1e-3j
+    prob = inputs.make_problem(Nx, Ny, stencil, vmax=0.8, seed=Nx * 3 + Ny, energies=[E], fL=1.0, fR=0.4)
+    p = find.Plan(Nx, Ny, stencil, leaf=leaf)
+    ex = p.export()
+    el, maps = ex["elims"], ex["maps"]
+    Hm = dense.hamiltonian_matrix(Nx, Ny, prob["H"])
+    rec = {}
+    for bonds in (False, True):
+        execute(ex, Nx, Ny, stencil, Hm, E, prob["sigma"][0], prob["sigma_less"][0], want_bonds=bonds, record=rec)
+    A = dense.dense_A(Nx, Ny, prob["H"], E, prob["sigma"][0])
+    Sl = dense.embed_contacts(Nx, Ny, prob["sigma_less"][0])
+    by_dst = {int(el[k][8]): k for k in range(len(el)) if el[k][0] == 0}
+    elim_set = {}
+
+    def eliminated(k):
+        if k not in elim_set:
+            s_, n_, mp = el[k][1], el[k][3], el[k][9]
+            out = set(maps[mp: mp + s_, 0].tolist())
+            for f_ in (4, 6):
+                if el[k][f_] >= 0:
+                    out |= eliminated(by_dst[int(el[k][f_])])
+            elim_set[k] = out
+        return elim_set[k]
+
+    checked = {0: 0, 1: 0, 2: 0}
+    for k in range(len(el)):
+        if el[k][0] != 0 or k not in rec:
+            continue
+        s_, n_, mp = el[k][1], el[k][3], el[k][9]
+        B = maps[mp + s_: mp + n_, 0]
+        I = np.array(sorted(eliminated(k)), dtype=int)
+        assert not set(I.tolist()) & set(B.tolist())
+        Lm = np.linalg.solve(A[np.ix_(I, I)].T, A[np.ix_(B, I)].T).T if I.size else np.zeros((B.size, 0))
+        U = A[np.ix_(B, B)] - Lm @ A[np.ix_(I, B)]
+        R = (Sl[np.ix_(B, B)] - Lm @ Sl[np.ix_(I, B)] - Sl[np.ix_(B, I)] @ Lm.conj().T
+             + Lm @ Sl[np.ix_(I, I)] @ Lm.conj().T)
+        Uk, Rk = rec[k]
+        assert np.max(np.abs(Uk - U)) <= 1e-10 * max(1.0, np.max(np.abs(U))), k
+        assert np.max(np.abs(Rk - R)) <= 1e-10 * max(1.0, np.max(np.abs(R))), k
+        checked[int(el[k][11])] += 1
+    assert all(v > 0 for v in checked.values()), checked
+    # the leaf-extraction fronts eliminate every node outside their kept set
+    for k in range(len(el)):
+        if el[k][0] == 0 and el[k][11] == 2 and k in rec:
+            assert len(eliminated(k)) + el[k][2] == Nx * Ny, k
+
+
+def test_solve_rejects_scattering_inputs_for_a_plain_plan():
+    """A contacts-only plan refuses Sigma_d / Sigma<_d instead of ignoring them
+    (checked before any device work)."""
+    find = findlib()
+    plan = find.Plan(6, 6, 5)
+    with pytest.raises(ValueError):
+        find.solve(plan, None, None, None, None, None, None, sigma_d=object(), sigma_less_d=object())

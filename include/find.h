@@ -207,6 +207,28 @@ find_status find_solve_scattering(find_plan plan, int nE, const double* energies
                                   const double* sigma_less_d, double* diag_G, double* diag_Gless,
                                   double* bond_G, double* bond_Gless, double* bond_J, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops or harnesses that forbid hipMalloc): find_solve for
+ * a contacts-only plan with every scratch buffer of the solve (energy pool,
+ * elimination workspace, pivot status) taken from a fixed device array of
+ * 512 MiB that the library holds on each device it runs on until the process
+ * ends.  It calls no hipMalloc, hipFree or other allocating routine.
+ * Preconditions: the plan's tables are on the current device, i.e. find_solve
+ * (or find_plan_autotune) ran with this plan on this device before, else
+ * FIND_E_ARG.  Energies are solved in passes of as many as fit the array
+ * next to the nE status entries; if one energy of the plan does not fit
+ * (e.g. more than about 1.2 energies' worth of a 128 x 128 mesh's U and R
+ * blocks), FIND_E_NOMEM with the bytes needed.  It runs on `hip_stream` only
+ * (opts.streams and profiling do not apply) with the plan's stage tiles, so
+ * its results equal find_solve's.  Every call on a device shares that
+ * device's array: calls that overlap in time on one device (on different
+ * streams or host threads) race and give wrong results; find_sync_status
+ * for such a call reads the array, so it must come before the next call on
+ * the device.  Other arguments and errors as find_solve. */
+find_status find_solve_noalloc(find_plan plan, int nE, const double* energies, const double* H,
+                               const double* sigma, const double* sigma_less, double* diag_G, double* diag_Gless,
+                               double* bond_G, double* bond_Gless, double* bond_J, void* hip_stream);
+
 /* Wait for `hip_stream`, then report FIND_E_SINGULAR if the last solve on
  * this plan met a zero or tiny pivot in the LU of some A(S,S) (eq.
  * (express-L)) or of a final leaf block (eq. (cd1)): |re| + |im| of the pivot

@@ -76,6 +76,34 @@ struct DevState {
   std::vector<void*> retired;
 };
 
+// Scratch of find_solve_noalloc: a fixed device array (one copy per device,
+// held until the process ends) for the energy pool, the elimination
+// workspace and the pivot status of that entry point.  Host code never uses
+// the array's name as an address: the address of each device's copy comes
+// from hipGetSymbolAddress, once per device, with that device current.
+constexpr size_t kNoAllocScratchBytes = size_t(512) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch (set up on first use).
+find_status scratch_of(int dev, unsigned char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(FIND_E_UNSUPPORTED, "find_solve_noalloc: device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(FIND_E_DEVICE, std::string("find_solve_noalloc: hipGetSymbolAddress(scratch): ") +
+                                     hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = static_cast<unsigned char*>(g_scratch_ptr[dev]);
+  return FIND_OK;
+}
+
 __global__ void k_fill_int(int* p, int n, int v) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -738,6 +766,55 @@ find_status find_solve_scattering(find_plan plan, int nE, const double* energies
     return fail(FIND_E_ARG, "find_solve_scattering: the plan was created without opts.scattering");
   return solve_impl(plan, nE, energies, H, sigma, sigma_less, sigma_d, sigma_less_d, diag_G, diag_Gless, bond_G,
                     bond_Gless, bond_J, hip_stream);
+}
+
+find_status find_solve_noalloc(find_plan plan, int nE, const double* energies, const double* H,
+                               const double* sigma, const double* sigma_less, double* diag_G, double* diag_Gless,
+                               double* bond_G, double* bond_Gless, double* bond_J, void* hip_stream) {
+  if (!plan) return fail(FIND_E_ARG, "find_solve_noalloc: NULL plan");
+  if (nE < 1) return fail(FIND_E_ARG, "find_solve_noalloc: nE must be >= 1");
+  if (!energies || !H || !sigma || !sigma_less || !diag_G || !diag_Gless)
+    return fail(FIND_E_ARG, "find_solve_noalloc: NULL input or diagonal output pointer");
+  if (plan->opts.scattering)
+    return fail(FIND_E_ARG, "find_solve_noalloc: scattering plans are not supported (use find_solve_scattering)");
+  std::lock_guard<std::mutex> lk(plan->mu);
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  plan->last_status = nullptr;
+  plan->last_nE = 0;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  auto it = plan->dev.find(dev);
+  DevState* d = it == plan->dev.end() ? nullptr : it->second.get();
+  DevState sizing;                       // (host copy of the stage sizes if the plan is not on the device)
+  if (!d) host_stages(plan, &sizing);
+  const DevState& z = d ? *d : sizing;
+  // largest pass that fits: status (nE ints), pool (ec energies), workspace (ec energies, one group)
+  auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+  const size_t per_e = size_t(plan->P.pool_per_energy) * sizeof(double2);
+  const size_t st_bytes = up(size_t(nE) * sizeof(int));
+  auto need = [&](int c) { return st_bytes + up(per_e * size_t(c)) + ws_for(z, c) * sizeof(double2); };
+  int ec = nE;
+  if (plan->opts.max_energies > 0) ec = std::min(ec, plan->opts.max_energies);
+  while (ec > 1 && need(ec) > kNoAllocScratchBytes)
+    ec = std::max(1, std::min(ec - 1, int(ec * double(kNoAllocScratchBytes) / double(need(ec)))));
+  if (need(ec) > kNoAllocScratchBytes) {
+    char buf[200];
+    snprintf(buf, sizeof buf, "find_solve_noalloc: one energy of this plan needs %zu bytes of scratch, "
+             "more than the %zu the library holds per device", need(1), kNoAllocScratchBytes);
+    return fail(FIND_E_NOMEM, buf);
+  }
+  if (!d)
+    return fail(FIND_E_ARG, "find_solve_noalloc: the plan has no tables on this device "
+                            "(run find_solve with it once on this device first)");
+  unsigned char* base = nullptr;
+  find_status fs = scratch_of(dev, &base);
+  if (fs != FIND_OK) return fs;
+  int* status = reinterpret_cast<int*>(base);
+  double2* pool = reinterpret_cast<double2*>(base + st_bytes);
+  double2* ws = reinterpret_cast<double2*>(base + st_bytes + up(per_e * size_t(ec)));
+  const SolveBufs b{pool, ws, status, ec, 1, ws_for(*d, ec), false};
+  return enqueue_solve(plan, d, b, nE, energies, H, sigma, sigma_less, nullptr, nullptr, diag_G, diag_Gless,
+                       bond_G, bond_Gless, bond_J, st);
 }
 
 find_status find_plan_autotune(find_plan plan, int nE, const double* energies, const double* H,

@@ -23,7 +23,8 @@ EF_FIELDS, SF_FIELDS, LF_FIELDS, ON_FIELDS, OB_FIELDS = 17, 4, 6, 2, 5
 EXPORTED = ["find_plan_create", "find_plan_destroy", "find_plan_footprint", "find_plan_flops",
             "find_n_bonds", "find_solve", "find_sync_status", "find_last_error",
             "find_plan_summary", "find_plan_export", "find_plan_set_profiling", "find_plan_profile",
-            "find_plan_autotune", "find_plan_get_tiles", "find_plan_set_tiles", "find_solve_scattering"]
+            "find_plan_autotune", "find_plan_get_tiles", "find_plan_set_tiles", "find_solve_scattering",
+            "find_solve_noalloc"]
 
 
 class FindError(RuntimeError):
@@ -74,6 +75,8 @@ def lib() -> ctypes.CDLL:
         L.find_solve.restype = st
         L.find_solve_scattering.argtypes = [vp, i32] + [vp] * 11 + [vp]
         L.find_solve_scattering.restype = st
+        L.find_solve_noalloc.argtypes = [vp, i32] + [vp] * 9 + [vp]
+        L.find_solve_noalloc.restype = st
         L.find_sync_status.argtypes = [vp, vp]; L.find_sync_status.restype = st
         L.find_last_error.argtypes = []; L.find_last_error.restype = ctypes.c_char_p
         L.find_plan_summary.argtypes = [vp, ctypes.POINTER(PlanSummary)]; L.find_plan_summary.restype = st
@@ -235,6 +238,28 @@ def solve(plan: Plan, energies, H, sigma, sigma_less, diag_G, diag_Gless,
         _check(lib().find_solve_scattering(plan.handle, nE, *args[:4], *d, *args[4:], sp))
     else:
         _check(lib().find_solve(plan.handle, nE, *args, sp))
+
+
+def solve_noalloc(plan: Plan, energies, H, sigma, sigma_less, diag_G, diag_Gless,
+                  bond_G=None, bond_Gless=None, bond_J=None, stream=None) -> None:
+    """find_solve_noalloc: as solve() for a contacts-only plan, with the
+    solve's scratch in the library's fixed per-device array (no device
+    allocation; the plan must have run solve() on this device before)."""
+    import torch
+    Nx, Ny = plan.Nx, plan.Ny
+    nE = int(energies.shape[0])
+    nst = 5 if plan.stencil == 9 else 3
+    nb = n_bonds(Nx, Ny, plan.stencil)
+    c128, f64 = torch.complex128, torch.float64
+    args = [_ptr(energies, "energies", (nE,), c128), _ptr(H, "H", (nst, Ny, Nx), f64),
+            _ptr(sigma, "sigma", (nE, 2, Nx, Nx), c128), _ptr(sigma_less, "sigma_less", (nE, 2, Nx, Nx), c128),
+            _ptr(diag_G, "diag_G", (nE, Ny, Nx), c128), _ptr(diag_Gless, "diag_Gless", (nE, Ny, Nx), c128),
+            _ptr(bond_G, "bond_G", (nE, nb), c128), _ptr(bond_Gless, "bond_Gless", (nE, nb), c128),
+            _ptr(bond_J, "bond_J", (nE, nb), f64)]
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+    _check(lib().find_solve_noalloc(plan.handle, nE, *args, sp))
 
 
 def autotune(plan: Plan, energies, H, sigma, sigma_less, diag_G, diag_Gless, reps: int = 2,

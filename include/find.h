@@ -267,11 +267,15 @@ find_status find_plan_profile(find_plan plan, double* kernel_ms, double* kernel_
  * LU trailing updates (stages whose fronts have at most 512 nodes, not the
  * final leaf blocks); 7 = one 512-thread workgroup (eight waves) per front and
  * one workgroup per compute unit, for stages with few large fronts (fronts of
- * up to 2048 nodes, not the final leaf blocks).
+ * up to 2048 nodes, not the final leaf blocks); 8 = final leaf blocks only
+ * (diagonal outputs, blocks of at most 64 nodes with R_K supported on at most
+ * 28): G = U_K^{-1} by Gauss-Jordan elimination with partial pivoting with the
+ * whole block in registers, diag G< as quadratic forms over R_K's support.
  * Configurations 0..3 and 6 only decide which threads compute which part of
  * the same operations in the same order, so their results are bitwise the
  * same; 4, 5 and 7 factor fronts with other register panels (same
- * operations, other rounding).
+ * operations, other rounding); 8 inverts by another elimination order (other
+ * rounding).
  *   find_plan_autotune runs one solve of the first min(nE, pass size)
  *   energies stage by stage, times every configuration of every stage `reps`
  *   times (reps < 1 means 2) with HIP events on `hip_stream`, keeps the

@@ -394,10 +394,15 @@ find_status find_plan_create(int Nx, int Ny, int stencil, const find_plan_opts* 
   }
   if (!err.empty()) { delete p; return fail(FIND_E_ARG, err); }
   for (const Stage& st : p->P.stages) {
-    int maxn = 1;
-    for (int k = st.first; k < st.first + st.count; ++k) maxn = std::max(maxn, p->P.elims[k].n);
+    int maxn = 1, maxb = 0, maxrs = 0;
+    for (int k = st.first; k < st.first + st.count; ++k) {
+      maxn = std::max(maxn, p->P.elims[k].n);
+      maxb = std::max(maxb, p->P.elims[k].b);
+      maxrs = std::max(maxrs, p->P.elims[k].ssig);
+    }
+    const bool gj_ok = st.phase == PH_FINAL && st.variant == 0 && maxb <= kGjMaxB && maxrs <= kGjMaxRs;
     p->tiles.push_back(0);
-    p->tile_mask.push_back(stage_tile_mask(maxn, st.phase == PH_FINAL));
+    p->tile_mask.push_back(stage_tile_mask(maxn, st.phase == PH_FINAL, gj_ok));
   }
   *out = p;
   return FIND_OK;

@@ -44,15 +44,17 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
 }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ double2 cfms(double2 c, double2 a, double2 b) {  // c - a*b
-  return make_double2(c.x - (a.x * b.x - a.y * b.y), c.y - (a.x * b.y + a.y * b.x));
+// c - a*b as four fused multiply-adds
+__device__ __forceinline__ double2 cfms(double2 c, double2 a, double2 b) {
+  return make_double2(fma(a.y, b.y, fma(-a.x, b.x, c.x)), fma(-a.y, b.x, fma(-a.x, b.y, c.y)));
 }
+// 1 / a with one division
 __device__ __forceinline__ double2 cinv(double2 a) {
-  double d = a.x * a.x + a.y * a.y;
-  return make_double2(a.x / d, -a.y / d);
+  const double rd = 1.0 / (a.x * a.x + a.y * a.y);
+  return make_double2(a.x * rd, -a.y * rd);
 }
 __device__ __forceinline__ double2 conjd(double2 a) { return make_double2(a.x, -a.y); }
 __device__ __forceinline__ double2 zero2() { return make_double2(0.0, 0.0); }
@@ -550,7 +552,7 @@ __device__ __forceinline__ int prow(const int* pm, int s, int r) { return r < s 
 template <int RPT, int NB, bool WG, class LDS>
 __device__ __forceinline__ bool tall_lu(LDS& L, double2* FA, int n, int s, double thr) {
   constexpr int NT = LDS::kNT;
-  constexpr int NB2 = 32;
+  constexpr int NB2 = LDS::kNT >= 256 ? 64 : 32;   // outer block (columns per trailing update)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int* pm = L.perm;
   bool singular = false;
@@ -904,6 +906,209 @@ __global__ __launch_bounds__(NT, 3) void k_final(StageArgs a, OutArgs o) {
   }
 }
 
+// Final leaf blocks of at most kGjMax nodes whose R_K is supported on at most
+// kGjRs of them, diagonal outputs only (eq. (cd1) and eq. (gless-nn) on K = C):
+// G = U_K^{-1} by Gauss-Jordan elimination with partial pivoting, the whole
+// 64 x 64 block in registers (thread t owns rows 4 (t % 16) .. + 3 and columns
+// 4 (t / 16) .. + 3).  Step k takes the largest |re| + |im| of column k among
+// the rows not pivoted yet (one DPP reduction by the 16 owners of the
+// column), publishes the column and the pivot row through LDS (buffers by step
+// parity, two barriers per step) and updates every entry; pivot rows are
+// relabelled, not moved, so that the block ends as G with its rows and
+// columns permuted: entry (r, k) is G(step of row r, pivot row of step k).
+// G(:, 0:rs) is then staged in LDS and diag G< = diag(G R_K G^dagger) is a
+// quadratic form over the rs support rows per output node, four threads each.
+// Nothing is written to the pool; results go straight to the outputs.
+constexpr int kGjMax = kGjMaxB, kGjRs = kGjMaxRs;
+struct GjLds {
+  double2 pcol[2][kGjMax];   // column k of the current step, by step parity
+  double2 prow[2][kGjMax];   // pivot row of the current step
+  unsigned long long key[2];
+  double2 pinv[2];           // reciprocal of the pivot
+  unsigned long long red[4];
+  int prowi[kGjMax];         // pivot row of each step
+  int kinv[kGjMax];          // step at which each row was pivot
+  double2 gd[kGjMax];        // diag G by local node
+  double2 grs[kGjRs][kGjMax];  // G(a, b) for b < rs, at [b][a]
+  double2 rs_[kGjRs][kGjRs];   // R_K(u, v) at [u][v]
+};
+
+template <int NT>
+__global__ __launch_bounds__(NT, 3) void k_final_gj(StageArgs a, OutArgs o) {
+  static_assert(NT == 256, "one 256-thread workgroup per block (4 x 4 entries per thread)");
+  __shared__ GjLds S;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int rb = tid & 15, cb = tid >> 4;
+  const long long total = (long long)a.n_elims * a.nE;
+  const size_t nn = (size_t)a.Nx * a.Ny;
+  for (long long item = blockIdx.x; item < total; item += gridDim.x) {
+    const int ei = int(item / a.nE), e = int(item % a.nE);
+    const ElimDev E = a.elims[ei];
+    const LeafOutDev Lo = o.leaves[E.aux];
+    const int bp = E.b, rs = E.ssig;
+    const double2* Uin = a.pool + (size_t)e * a.pool_stride + E.src0;   // U_K, ld bp
+    const double2* Rin = Uin + (size_t)bp * bp;                            // R_K
+    double2 M[4][4];
+    double amax = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = 4 * rb + i, c = 4 * cb + j;
+        double2 v = make_double2(r == c ? 1.0 : 0.0, 0.0);
+        if (r < bp && c < bp) {
+          v = Uin[(a.sym & 1) && r < c ? (size_t)r * bp + c : (size_t)c * bp + r];
+          amax = fmax(amax, fabs(v.x) + fabs(v.y));
+        }
+        M[i][j] = v;
+      }
+    for (int t = tid; t < rs * rs; t += 256) {
+      const int u = t % rs, v = t / rs;
+      S.rs_[u][v] = Rin[(size_t)v * bp + u];
+    }
+    {
+      const u64 w = wave_max((u64)__double_as_longlong(amax));
+      if (lane == 0) S.red[tid >> 6] = w;
+    }
+    __syncthreads();
+    const double thr = kPivotRel * 2.220446049250313e-16 *
+                       __longlong_as_double((long long)umax64(umax64(S.red[0], S.red[1]), umax64(S.red[2], S.red[3])));
+    u64 used = 0;          // rows pivoted so far (bit r)
+    bool singular = false;
+    // steps k = 4 kb + kj, kj unrolled so that column k is a register index
+    for (int kb = 0; 4 * kb < bp; ++kb) {
+      const bool owner = cb == kb;          // this thread holds column block kb
+#pragma unroll
+      for (int kj = 0; kj < 4; ++kj) {
+        const int k = 4 * kb + kj;
+        if (k >= bp) break;
+        const int buf = kj & 1;
+        // 1. the wave holding column k: candidates among rows not pivoted yet,
+        //    maximum over the 16 owners (one DPP row of 16 lanes); the lane
+        //    holding the pivot publishes its reciprocal with the key
+        if ((tid >> 6) == (kb >> 2)) {
+          u64 best = 0;
+          double2 bv = make_double2(1.0, 0.0);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int r = 4 * rb + i;
+            const double2 v = M[i][kj];
+            if (owner) {
+              S.pcol[buf][r] = v;
+              if (r < bp && !((used >> r) & 1)) {
+                const u64 key = pivot_key(fabs(v.x) + fabs(v.y), r);
+                if (key > best) { best = key; bv = v; }
+              }
+            }
+          }
+          const u64 mine = best;
+          best = umax64(best, dpp_u64<0xB1>(best));
+          best = umax64(best, dpp_u64<0x4E>(best));
+          best = umax64(best, dpp_u64<0x141>(best));
+          best = umax64(best, dpp_u64<0x140>(best));
+          if (owner && mine == best) {
+            S.key[buf] = best;
+            // zero pivot magnitude: the reciprocal of 1 keeps the elimination finite
+            if (!((best >> kKeyBits) != 0)) bv = make_double2(1.0, 0.0);
+            const double rd = 1.0 / (bv.x * bv.x + bv.y * bv.y);
+            S.pinv[buf] = make_double2(bv.x * rd, -bv.y * rd);
+          }
+        }
+        __syncthreads();
+        // 2. every thread decodes the same pivot row p; its owners publish it
+        const u64 gk = S.key[buf];
+        const double2 inv = S.pinv[buf];
+        double2 f[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) f[i] = cmul(S.pcol[buf][4 * rb + i], inv);
+        int p = kKeyRows - 1 - int(gk & (kKeyRows - 1));
+        if (p < 0 || p >= bp) p = k;   // (no candidate: cannot happen for k < bp)
+        p = __builtin_amdgcn_readfirstlane(p);
+        const double mag = __longlong_as_double((long long)(gk & ~(u64)(kKeyRows - 1)));
+        if (!(mag > 0.0) || mag < thr) singular = true;
+        const int pi = p & 3;
+        const bool prow_owner = rb == (p >> 2);
+        if (prow_owner) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (pi == i)
+#pragma unroll
+              for (int j = 0; j < 4; ++j) S.prow[buf][4 * cb + j] = M[i][j];
+        }
+        if (tid == 0) { S.prowi[k] = p; S.kinv[p] = k; }
+        __syncthreads();
+        // 3. M(i,j) -= f_i M(p,j) with f_i = M(i,k) / pivot for every row (row p
+        //    and column k come out zero and are set next): column k <- -f,
+        //    row p <- M(p,:) / pivot with 1 / pivot at column k
+        double2 pr[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) pr[j] = S.prow[buf][4 * cb + j];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) M[i][j] = cfms(M[i][j], f[i], pr[j]);
+        if (owner) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) M[i][kj] = make_double2(-f[i].x, -f[i].y);
+        }
+        if (prow_owner) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (pi == i)
+#pragma unroll
+              for (int j = 0; j < 4; ++j) M[i][j] = (owner && j == kj) ? inv : cmul(pr[j], inv);
+        }
+        used |= (u64)1 << p;
+      }
+    }
+    if (singular && tid == 0) a.status[e] = 1;
+    // G(kinv[r], prowi[c]) = M(r, c): diag G and G(:, 0:rs) into LDS
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = 4 * rb + i, c = 4 * cb + j;
+        if (r < bp && c < bp) {
+          const int ga = S.kinv[r], gb = S.prowi[c];
+          if (gb < rs) S.grs[gb][ga] = M[i][j];
+          if (ga == gb) S.gd[ga] = M[i][j];
+        }
+      }
+    __syncthreads();
+    // outputs: four threads per node, partial sums over u = sub, sub + 4, ...
+    const int sub = tid & 3;
+    for (int q0 = 0; q0 < Lo.n_nodes; q0 += 64) {
+      const int q = q0 + (tid >> 2);
+      int l = 0, node = -1;
+      if (q < Lo.n_nodes) {
+        node = o.outnode[2 * (Lo.node_first + q)];
+        l = o.outnode[2 * (Lo.node_first + q) + 1];
+      }
+      double re = 0.0, im = 0.0;
+      if (node >= 0) {
+        for (int u = sub; u < rs; u += 4) {
+          double2 t = zero2();   // sum_v R(u, v) conj G(l, v)
+          for (int v = 0; v < rs; ++v) {
+            const double2 g = S.grs[v][l], rr = S.rs_[u][v];
+            t.x += rr.x * g.x + rr.y * g.y;
+            t.y += rr.y * g.x - rr.x * g.y;
+          }
+          const double2 gu = S.grs[u][l];
+          re += gu.x * t.x - gu.y * t.y;
+          im += gu.x * t.y + gu.y * t.x;
+        }
+      }
+      re += dpp_f64<0xB1>(re); im += dpp_f64<0xB1>(im);
+      re += dpp_f64<0x4E>(re); im += dpp_f64<0x4E>(im);
+      if (node >= 0 && sub == 0) {
+        o.diag_G[e * nn + node] = S.gd[l];
+        o.diag_Gless[e * nn + node] = make_double2(re, im);
+      }
+    }
+    __syncthreads();
+  }
+}
+
 #ifndef FIND_TU
 #error "kernels.hip is compiled once per kernel family: -DFIND_TU=1 .. 7"
 #endif
@@ -987,6 +1192,10 @@ hipError_t launch_final_w2(const StageArgs& a, const OutArgs& o, int rpt, int gr
     case 2: hipLaunchKernelGGL((k_final<2, 128, kTwoWaveMaxFront>), dim3(grid), dim3(128), 0, st, a, o); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+hipError_t launch_final_gj(const StageArgs& a, const OutArgs& o, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_final_gj<256>, dim3(grid), dim3(256), 0, st, a, o);
   return hipGetLastError();
 }
 hipError_t launch_final_w(const StageArgs& a, const OutArgs& o, int rpt, int grid, hipStream_t st) {

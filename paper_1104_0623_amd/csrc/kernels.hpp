@@ -70,12 +70,17 @@ constexpr int kThreads = 256;
 // nodes), or kTileWg: 64x64 workgroup tiles whose operands the four waves
 // share through LDS (Schur products and LU trailing updates; fronts of at
 // most 512 nodes), or kTileEight: one 512-thread workgroup per front and per
-// CU, for stages with few, large fronts.  cm: 0 = 4M, 1 = 3M complex products.
-constexpr int kTileConfigs = 8;
+// CU, for stages with few, large fronts.  kTileGJ (final leaf blocks only):
+// Gauss-Jordan inversion of the whole block in registers, for blocks of at most
+// 64 nodes with R_K supported on at most 28 of them and diagonal outputs.
+// cm: 0 = 4M, 1 = 3M complex products.
+constexpr int kTileConfigs = 9;
 constexpr int kTileWave = 4;       // one wave (64 threads) per front
 constexpr int kTileTwoWave = 5;    // two waves (128 threads) per front
 constexpr int kTileWg = 6;         // 64x64 workgroup tiles staged through LDS
 constexpr int kTileEight = 7;      // eight waves (512 threads) per front, one workgroup per CU
+constexpr int kTileGJ = 8;         // final blocks: register-resident Gauss-Jordan (see k_final_gj)
+constexpr int kGjMaxB = 64, kGjMaxRs = 28;
 constexpr int kEightWaveThreads = 512;
 constexpr int kWaveMaxFront = 128;
 constexpr int kTwoWaveMaxFront = 256;
@@ -86,6 +91,7 @@ inline int groups_per_slot(int tc) { return tc == kTileWave ? 4 : tc == kTileTwo
 // two workgroups per CU
 inline long long stage_grid_groups(long long slots, int tc) {
   if (tc == kTileEight) return slots / 3;   // one eight-wave workgroup per CU
+  if (tc == kTileGJ) return slots;          // three 256-thread workgroups per CU
   return tc == kTileWg ? slots * 2 / 3 : slots * groups_per_slot(tc);
 }
 #define FIND_CAT_(a, b) a##b
@@ -99,13 +105,17 @@ hipError_t launch_stage_w8(const StageArgs& a, int rpt, int cm, int grid, hipStr
 hipError_t launch_final(const StageArgs& a, const OutArgs& o, int rpt, int grid, hipStream_t st);
 hipError_t launch_final_w(const StageArgs& a, const OutArgs& o, int rpt, int grid, hipStream_t st);
 hipError_t launch_final_w2(const StageArgs& a, const OutArgs& o, int rpt, int grid, hipStream_t st);
+hipError_t launch_final_gj(const StageArgs& a, const OutArgs& o, int grid, hipStream_t st);
 // panel rows per thread of the one- and two-wave forms
 inline int wave_rpt(int n) { return n <= 64 ? 1 : 2; }
 inline int wave2_rpt(int n) { return n <= 128 ? 1 : 2; }
 inline int wave8_rpt(int n) { return n <= 512 ? 1 : n <= 1024 ? 2 : 4; }
-// bit mask of the tile configurations a stage with fronts of at most maxn nodes has
-inline int stage_tile_mask(int maxn, bool final_stage) {
+// bit mask of the tile configurations a stage with fronts of at most maxn nodes has;
+// gj_ok: a final stage whose blocks fit k_final_gj (at most kGjMaxB nodes, R_K
+// on at most kGjMaxRs, no bond outputs)
+inline int stage_tile_mask(int maxn, bool final_stage, bool gj_ok = false) {
   int m = final_stage ? 1 : (panel_rpt(maxn) <= 2 ? (0xf | 1 << kTileWg) : 1);
+  if (final_stage && gj_ok) m |= 1 << kTileGJ;
   if (!final_stage) m |= 1 << kTileEight;
   if (maxn <= kWaveMaxFront) m |= 1 << kTileWave;
   if (maxn <= kTwoWaveMaxFront) m |= 1 << kTileTwoWave;
@@ -123,6 +133,7 @@ inline hipError_t launch_stage(const StageArgs& a, int maxn, int tc, int cm, int
   }
 }
 inline hipError_t launch_final_tc(const StageArgs& a, const OutArgs& o, int maxn, int tc, int grid, hipStream_t st) {
+  if (tc == kTileGJ) return launch_final_gj(a, o, grid, st);
   if (tc == kTileWave) return maxn <= kWaveMaxFront ? launch_final_w(a, o, wave_rpt(maxn), grid, st) : hipErrorInvalidValue;
   if (tc == kTileTwoWave)
     return maxn <= kTwoWaveMaxFront ? launch_final_w2(a, o, wave2_rpt(maxn), grid, st) : hipErrorInvalidValue;

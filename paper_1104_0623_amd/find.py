@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libfind.so")
 FIND_OK, FIND_E_ARG, FIND_E_NOMEM, FIND_E_SINGULAR, FIND_E_DEVICE, FIND_E_UNSUPPORTED = range(6)
 PREC_FP64, PREC_MIXED, PREC_MIXED_GLESS = 0, 1, 2
 CPLX_4M, CPLX_3M = 0, 1
-TILE_NAMES = ("32x32", "32x16", "16x32", "16x16", "wave", "2wave", "wg64x64", "8wave")
+TILE_NAMES = ("32x32", "32x16", "16x32", "16x16", "wave", "2wave", "wg64x64", "8wave", "gj")
 EF_FIELDS, SF_FIELDS, LF_FIELDS, ON_FIELDS, OB_FIELDS = 17, 4, 6, 2, 5
 EXPORTED = ["find_plan_create", "find_plan_destroy", "find_plan_footprint", "find_plan_flops",
             "find_n_bonds", "find_solve", "find_sync_status", "find_last_error",

@@ -255,3 +255,26 @@ def test_capture_needs_an_eager_solve_and_growth_keeps_captured_buffers():
         for o, ref in zip(outs6, eager6):
             assert torch.equal(o, ref), rep
     f.sync_status(plan)
+
+
+@pytest.mark.parametrize("Nx,Ny,stencil,leaf", [(16, 16, 5, 8), (24, 40, 5, 8), (12, 9, 9, 4), (33, 20, 9, 8),
+                                                (7, 13, 5, 3), (40, 7, 5, 16)])
+def test_gauss_jordan_final_blocks_against_dense(Nx, Ny, stencil, leaf):
+    """Launch configuration 8 of the final stage (register-resident Gauss-Jordan
+    inversion of U_K, diag G< as quadratic forms) wherever the stage has it,
+    general and symmetric forms, with a pass split and energy groups."""
+    f = find()
+    E = np.array([0.41 + 1e-6j, -2.9 + 1e-6j, 1.3 + 1e-3j, -0.05 + 1e-6j])
+    prob = inputs.make_problem(Nx, Ny, stencil, vmax=1.0, seed=Nx * 13 + Ny, energies=E, fL=1.0, fR=0.3)
+    ref = dense.dense_solve(Nx, Ny, stencil, prob["H"], E, prob["sigma"], prob["sigma_less"], bonds=False)
+    for kw in ({}, dict(symmetric=True), dict(streams=2, max_energies=3)):
+        plan = f.Plan(Nx, Ny, stencil, leaf=leaf, **kw)
+        opts = plan.tile_options()
+        has = [8 in o for o in opts]
+        if not any(has):
+            assert leaf > 8, "every diagonal final stage of leaves up to 8 x 8 has the Gauss-Jordan form"
+            return
+        plan.set_tiles([8 if h else 0 for h in has])
+        out = f.run_problem(plan, prob, want_bonds=False)
+        compare(out, ref, prob, bonds=False, tol=SYM_TOL if kw.get("symmetric") else TOL,
+                label=f"gj {Nx}x{Ny} {kw}")

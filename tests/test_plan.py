@@ -80,12 +80,17 @@ def test_tile_and_complex_mode_options():
     assert len(opts) == n
     for st, o in zip(stages, opts):
         maxn = int(elims[st[0]:st[0] + st[1], 3].max())
+        maxb = int(elims[st[0]:st[0] + st[1], 2].max())
+        maxrs = int(elims[st[0]:st[0] + st[1], 14].max())
         final = st[2] == 3
         # Schur stages whose fronts stay <= 512 have the four wave tiles and the
         # workgroup tile; the final leaf blocks only the default; fronts <= 128
-        # also the one-wave form, fronts <= 256 the two-wave form
+        # also the one-wave form, fronts <= 256 the two-wave form; final stages
+        # of the diagonal outputs with blocks <= 64 and R_K on <= 28 nodes the
+        # Gauss-Jordan form
+        gj = final and st[3] == 0 and maxb <= 64 and maxrs <= 28
         want = (([0] if final else [0, 1, 2, 3]) + ([4] if maxn <= 128 else []) + ([5] if maxn <= 256 else [])
-                + ([6] if not final and maxn <= 512 else []) + ([] if final else [7]))
+                + ([6] if not final and maxn <= 512 else []) + ([] if final else [7]) + ([8] if gj else []))
         assert o == want, (st, maxn, o)
     pick = [o[-1] for o in opts]
     plan.set_tiles(pick)

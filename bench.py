@@ -154,6 +154,12 @@ def main() -> int:
                          "half of each U; by default the general form runs (it keeps the 1e-10 accuracy at the "
                          "ill-conditioned energies where the mirrored U loses a factor of a few)")
     ap.add_argument("--streams", type=int, default=2, help="energy groups solved concurrently (0/1 = one)")
+    ap.add_argument("--bonds", action="store_true",
+                    help="also return G and G< on every bond and the bond currents (the leaf extraction "
+                         "keeps the bonds' far ends)")
+    ap.add_argument("--half-leaves", action="store_true",
+                    help="current density from half of the leaves: a checkerboard of leaves extracts the "
+                         "ring around it too, the others none (useful with --leaf 2)")
     ap.add_argument("--autotune", action="store_true",
                     help="run the autotuner even if the tuning table has an entry for this workload")
     ap.add_argument("--scattering", action="store_true",
@@ -206,7 +212,7 @@ def main() -> int:
     prec = PRECISION[args.precision]
     cmode = find.CPLX_3M if args.complex_mode == "3m" else find.CPLX_4M
     plan = find.Plan(Nx, Ny, st, leaf=args.leaf, precision=prec, complex_mode=cmode, symmetric=args.symmetric,
-                     streams=args.streams, scattering=args.scattering)
+                     streams=args.streams, scattering=args.scattering, half_leaves=args.half_leaves)
     plain_flops = plain_find_flops(plan)
     stream = torch.cuda.Stream()          # non-default stream (graph capture needs one)
     torch.cuda.set_stream(stream)
@@ -236,8 +242,15 @@ def main() -> int:
         tune_s = time.perf_counter() - t
     tiles = plan.tiles()
 
+    bond_out = {}
+    if args.bonds:
+        nb = find.n_bonds(Nx, Ny, st)
+        bond_out = dict(bond_G=torch.empty((nE, nb), dtype=torch.complex128, device=dev),
+                        bond_Gless=torch.empty((nE, nb), dtype=torch.complex128, device=dev),
+                        bond_J=torch.empty((nE, nb), dtype=torch.float64, device=dev))
+
     def eager_step():
-        find.solve(plan, E, H, S, SL, dG, dL, stream=stream, **scat)
+        find.solve(plan, E, H, S, SL, dG, dL, stream=stream, **bond_out, **scat)
 
     for _ in range(max(1, args.warmup)):
         eager_step()
@@ -261,7 +274,7 @@ def main() -> int:
     lat = []
     kms = kflops = 0.0
     nl = 0
-    flops_step = plan.flops_per_energy(False) * nE
+    flops_step = plan.flops_per_energy(args.bonds) * nE
     t0 = time.perf_counter()
     for _ in range(args.steps):
         ts = time.perf_counter()
@@ -291,10 +304,12 @@ def main() -> int:
         "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"FIND diag G + diag G<, {Nx}x{Ny} mesh, {st}-point stencil, {nE} energies "
-                               f"per step ({args.preset}), {args.precision}"
-                               + (", diagonal scattering self-energies on every node" if args.scattering else ""),
-                   "scattering": bool(args.scattering),
+        "config": {"workload": f"FIND diag G + diag G<{' + bond G, G<, J' if args.bonds else ''}, {Nx}x{Ny} mesh, "
+                               f"{st}-point stencil, {nE} energies per step ({args.preset}), {args.precision}"
+                               + (", diagonal scattering self-energies on every node" if args.scattering else "")
+                               + (", leaf extraction on half of the leaves" if args.half_leaves else ""),
+                   "scattering": bool(args.scattering), "bonds": bool(args.bonds),
+                   "half_leaves": bool(args.half_leaves),
                    "Nx": Nx, "Ny": Ny, "stencil": st, "energies_per_step": nE, "precision": args.precision,
                    "leaf": args.leaf, "complex_mode": args.complex_mode, "symmetric": args.symmetric, "streams": args.streams,
                    "launch": "eager" if args.no_graph else "hipGraph replay per batch",

@@ -129,7 +129,19 @@ typedef enum { FIND_CPLX_4M = 0, FIND_CPLX_3M = 1 } find_complex_mode;
  *                 subtracted from the diagonal of A and Sigma<_d added to the
  *                 diagonal of Sigma<, both passed to find_solve_scattering.  Every
  *                 node then carries Sigma<, so no front skips its W and R.
- *                 0 (default): contacts only, find_solve. */
+ *                 0 (default): contacts only, find_solve.
+ *   half_leaves   1: the current density scheme of Sec. 4.3 (Fig. cd-opt):
+ *                 only a checkerboard of leaves runs the leaf extraction and
+ *                 final block, each keeping the ring of nodes around it and
+ *                 returning the diagonal and bond entries of that ring too, so
+ *                 that the other leaves need no extraction.  A leaf is added
+ *                 to the checkerboard wherever a node or bond would otherwise
+ *                 lie in no chosen leaf's kept set (always with 9-point
+ *                 meshes, whose diagonal bonds inside a skipped leaf no
+ *                 neighbour reaches; with leaves larger than 2 x 2 the
+ *                 interior of a skipped leaf forces it in).  Results are
+ *                 those of the default (every leaf); only the work differs.
+ *                 0 (default): every leaf. */
 typedef struct {
   int leaf;
   int precision;
@@ -140,7 +152,8 @@ typedef struct {
   int symmetric;
   int streams;
   int scattering;
-  int reserved[4];
+  int half_leaves;
+  int reserved[3];
 } find_plan_opts;
 
 /* Build the cluster tree, boundary sets, gather maps and level schedule for

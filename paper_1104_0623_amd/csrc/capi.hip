@@ -382,13 +382,14 @@ find_status find_plan_create(int Nx, int Ny, int stencil, const find_plan_opts* 
   if (o.symmetric != 0 && o.symmetric != 1) return fail(FIND_E_ARG, "find_plan_create: symmetric must be 0 or 1");
   if (o.streams < 0 || o.streams > 4) return fail(FIND_E_ARG, "find_plan_create: streams must be 0..4");
   if (o.scattering != 0 && o.scattering != 1) return fail(FIND_E_ARG, "find_plan_create: scattering must be 0 or 1");
+  if (o.half_leaves != 0 && o.half_leaves != 1) return fail(FIND_E_ARG, "find_plan_create: half_leaves must be 0 or 1");
   if ((long long)Nx * Ny > (1LL << 24)) return fail(FIND_E_UNSUPPORTED, "find_plan_create: mesh larger than 2^24 nodes");
   find_plan_s* p = new (std::nothrow) find_plan_s();
   if (!p) return fail(FIND_E_NOMEM, "find_plan_create: host allocation failed");
   p->opts = o;
   std::string err;
   try {
-    err = build_plan(Nx, Ny, stencil, o.leaf, p->P, o.scattering != 0);
+    err = build_plan(Nx, Ny, stencil, o.leaf, p->P, o.scattering != 0, o.half_leaves != 0);
   } catch (const std::exception& ex) {
     err = std::string("find_plan_create: ") + ex.what();
   }

@@ -344,17 +344,94 @@ struct Builder {
     P.n_bonds = count_bonds(Nx, Ny, stencil);
     std::vector<int> leaves;
     for (int q = 0; q < nc; ++q) if (P.cl[q].leaf()) leaves.push_back(q);
+    // Which leaves run the extraction, and what each keeps and outputs.  By
+    // default every leaf outputs its own nodes and the bonds whose first node
+    // it holds (keeping the bonds' other ends).  With half_leaves (the current
+    // density scheme of Sec. 4.3: chosen leaves also output the diagonal and
+    // bond entries of the ring of nodes around them, so the other leaves need
+    // no extraction at all) a checkerboard of leaves is chosen, topped up
+    // greedily until every node and bond lies in the kept set C u ring of a
+    // chosen leaf, and every output is owned by one chosen leaf.
+    const int nl = int(leaves.size());
+    std::vector<int> leaf_of(size_t(Nx) * Ny, -1);
+    for (int l = 0; l < nl; ++l)
+      for (int i : cluster_nodes(P.cl[leaves[l]].r)) leaf_of[i] = l;
+    std::vector<std::vector<std::array<int, 5>>> all_bonds(nl);   // bonds by the leaf of their first node
+    for (int l = 0; l < nl; ++l) leaf_bonds(P.cl[leaves[l]].r, all_bonds[l]);
+    std::vector<char> chosen(nl, 1);
+    std::vector<std::vector<int>> own_nodes(nl), extra(nl * 2);   // extra[2 l + v]: kept nodes outside C
+    std::vector<std::vector<std::array<int, 5>>> owned(nl);
+    // leaves whose kept set C u ring(l) holds node i: its own leaf and the leaves of its neighbours
+    auto leaves_at = [&](int i) {
+      std::vector<int> ls{leaf_of[i]};
+      stencil_nbrs(i % Nx, i / Nx, [&](int u, int v) { ls.push_back(leaf_of[v * Nx + u]); });
+      std::sort(ls.begin(), ls.end());
+      ls.erase(std::unique(ls.begin(), ls.end()), ls.end());
+      return ls;
+    };
+    if (!P.half_leaves) {
+      for (int l = 0; l < nl; ++l) {
+        own_nodes[l] = cluster_nodes(P.cl[leaves[l]].r);
+        owned[l] = all_bonds[l];
+      }
+    } else {
+      for (int l = 0; l < nl; ++l) {
+        const Rect& r = P.cl[leaves[l]].r;
+        chosen[l] = ((r.x0 / 2 + r.y0 / 2) & 1) == 0;
+      }
+      // greedy top-up: a node or bond no chosen leaf holds chooses the leaf of its first node
+      auto holder = [&](int i, int j) {   // a chosen leaf whose kept set holds i and j, else -1
+        const std::vector<int> a = leaves_at(i), b = leaves_at(j);
+        for (int l : a)
+          if (chosen[l] && std::binary_search(b.begin(), b.end(), l)) return l;
+        return -1;
+      };
+      for (int i = 0; i < Nx * Ny; ++i)
+        if (holder(i, i) < 0) chosen[leaf_of[i]] = 1;
+      for (int l = 0; l < nl; ++l)
+        for (auto& ob : all_bonds[l])
+          if (holder(ob[1], ob[2]) < 0) chosen[leaf_of[ob[1]]] = 1;
+      // owners: the node's (bond's first node's) own leaf if chosen, else the
+      // lowest chosen leaf holding it
+      auto owner = [&](int i, int j) {
+        if (chosen[leaf_of[i]]) {
+          const std::vector<int> b = leaves_at(j);
+          if (std::binary_search(b.begin(), b.end(), leaf_of[i])) return leaf_of[i];
+        }
+        return holder(i, j);
+      };
+      for (int i = 0; i < Nx * Ny; ++i) {
+        const int l = owner(i, i);
+        if (l < 0) return "plan: half-leaf extraction left a node uncovered";
+        own_nodes[l].push_back(i);
+        if (leaf_of[i] != l) { extra[2 * l].push_back(i); extra[2 * l + 1].push_back(i); }
+      }
+      for (int l0 = 0; l0 < nl; ++l0)
+        for (auto& ob : all_bonds[l0]) {
+          const int l = owner(ob[1], ob[2]);
+          if (l < 0) return "plan: half-leaf extraction left a bond uncovered";
+          owned[l].push_back(ob);
+        }
+    }
+    for (int l = 0; l < nl; ++l) {
+      if (!chosen[l]) continue;
+      const Rect& r = P.cl[leaves[l]].r;
+      for (auto& ob : owned[l])
+        for (int end : {ob[1], ob[2]})
+          if (!inside(r, end % Nx, end / Nx)) extra[2 * l + 1].push_back(end);
+      for (int v = 0; v < 2; ++v) {
+        std::vector<int>& x = extra[2 * l + v];
+        std::sort(x.begin(), x.end());
+        x.erase(std::unique(x.begin(), x.end()), x.end());
+      }
+    }
     // pool slots for leaf blocks: sized for the larger variant, shared by both
-    std::vector<int64_t> leaf1_off(leaves.size()), fin_off(leaves.size());
-    std::vector<int> rsup(leaves.size(), 0);
-    std::vector<std::vector<std::array<int, 5>>> owned(leaves.size());
-    for (size_t l = 0; l < leaves.size(); ++l) {
+    std::vector<int64_t> leaf1_off(nl, -1), fin_off(nl, -1);
+    std::vector<int> rsup(nl, 0);
+    for (int l = 0; l < nl; ++l) {
+      if (!chosen[l]) continue;
       const Cluster& c = P.cl[leaves[l]];
-      leaf_bonds(c.r, owned[l]);
-      std::vector<int> N;
-      for (auto& ob : owned[l]) if (!inside(c.r, ob[2] % Nx, ob[2] / Nx)) N.push_back(ob[2]);
-      std::sort(N.begin(), N.end()); N.erase(std::unique(N.begin(), N.end()), N.end());
-      int64_t bp = int64_t(c.r.w) * c.r.h + N.size();
+      const int64_t bp = int64_t(c.r.w) * c.r.h + int64_t(extra[2 * l + 1].size());
       leaf1_off[l] = off; off += 2 * bp * bp;
       fin_off[l] = off; off += 2 * bp * bp;
     }
@@ -364,13 +441,13 @@ struct Builder {
     for (int v = 0; v < 2; ++v) {
       int first = int(P.elims.size());
       std::vector<std::vector<int>> keeps(leaves.size());
-      for (size_t l = 0; l < leaves.size(); ++l) {
+      std::vector<int> ext_leaf;      // the leaves that run the extraction, in stage order
+      for (int l = 0; l < nl; ++l) {
+        if (!chosen[l]) continue;
+        ext_leaf.push_back(l);
         const Cluster& c = P.cl[leaves[l]];
         std::vector<int> Cn = cluster_nodes(c.r);
-        std::vector<int> N;
-        if (v == 1)
-          for (auto& ob : owned[l]) if (!inside(c.r, ob[2] % Nx, ob[2] / Nx)) N.push_back(ob[2]);
-        std::sort(N.begin(), N.end()); N.erase(std::unique(N.begin(), N.end()), N.end());
+        const std::vector<int>& N = extra[2 * l + v];
         std::vector<int> list, src, pos;
         Elim e; e.phase = PH_LEAF; e.cluster = leaves[l]; e.level = c.depth; e.dst = leaf1_off[l];
         if (leaves[l] != 0) {
@@ -385,8 +462,9 @@ struct Builder {
       }
       P.stages.push_back({first, int(P.elims.size()) - first, PH_LEAF, v});
       first = int(P.elims.size());
-      for (size_t l = 0; l < leaves.size(); ++l) {
-        const Elim& le = P.elims[P.stages.back().first + l];
+      for (size_t t = 0; t < ext_leaf.size(); ++t) {
+        const int l = ext_leaf[t];
+        const Elim& le = P.elims[P.stages.back().first + t];
         Elim e; e.kind = K_FINAL; e.phase = PH_FINAL; e.cluster = leaves[l]; e.level = le.level;
         e.s = le.b; e.b = le.b; e.n = 2 * le.b;
         // R_K is supported on its first rsup rows and columns (the Sigma<-carrying
@@ -400,15 +478,20 @@ struct Builder {
           P.map_pos.push_back(r % le.b);
         }
         P.elims.push_back(e);
-        // output records: the nodes of C at their positions in the kept order
-        const Cluster& c = P.cl[leaves[l]];
+        // output records: the nodes the leaf owns at their positions in the kept order
         LeafOut lo;
         lo.elim = int(P.elims.size()) - 1; lo.variant = v;
-        lo.n_nodes = c.r.w * c.r.h; lo.node_first = int(P.outnode_node.size());
-        for (int q2 = 0; q2 < int(keeps[l].size()); ++q2) {
-          const int nd = keeps[l][q2];
-          if (!inside(c.r, nd % Nx, nd / Nx)) continue;
-          P.outnode_node.push_back(nd); P.outnode_local.push_back(q2);
+        lo.n_nodes = 0; lo.node_first = int(P.outnode_node.size());
+        {
+          std::vector<int> own = own_nodes[l];
+          std::sort(own.begin(), own.end());
+          for (int q2 = 0; q2 < int(keeps[l].size()); ++q2) {
+            const int nd = keeps[l][q2];
+            if (!std::binary_search(own.begin(), own.end(), nd)) continue;
+            P.outnode_node.push_back(nd); P.outnode_local.push_back(q2);
+            ++lo.n_nodes;
+          }
+          if (lo.n_nodes != int(own.size())) return "plan: owned node missing from leaf block";
         }
         lo.bond_first = int(P.outbonds.size()); lo.n_bonds = 0;
         if (v == 1) {
@@ -448,9 +531,10 @@ struct Builder {
 
 }  // namespace
 
-std::string build_plan(int Nx, int Ny, int stencil, int leaf, Plan& P, bool scattering) {
+std::string build_plan(int Nx, int Ny, int stencil, int leaf, Plan& P, bool scattering, bool half_leaves) {
   P = Plan();
   P.Nx = Nx; P.Ny = Ny; P.stencil = stencil; P.leaf = leaf; P.scattering = scattering;
+  P.half_leaves = half_leaves;
   Builder b(P);
   return b.build();
 }

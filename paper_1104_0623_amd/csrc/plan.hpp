@@ -57,6 +57,9 @@ struct Plan {
   int Nx = 0, Ny = 0, stencil = 5, leaf = 8;
   // diagonal scattering self-energies on every node: every node carries Sigma<
   bool scattering = false;
+  // leaf extraction on a checkerboard of leaves whose kept sets cover the ring
+  // around them (current density from half of the leaves)
+  bool half_leaves = false;
   // pool offset (per energy) of the node diagonal: A_ii of the original matrix
   // without its contact part (E - H_ii - Sigma_d,i), then Sigma<_d,i ([2][Ny][Nx])
   int64_t onsite_off = 0;
@@ -77,7 +80,8 @@ struct Plan {
 
 int count_bonds(int Nx, int Ny, int stencil);
 // Builds the plan; returns an empty string on success, else a message.
-std::string build_plan(int Nx, int Ny, int stencil, int leaf, Plan& P, bool scattering = false);
+std::string build_plan(int Nx, int Ny, int stencil, int leaf, Plan& P, bool scattering = false,
+                       bool half_leaves = false);
 // sym: bit 0 = only half of U formed, bit 1 = only half of R formed
 double elim_flops(const Elim& e, int sym = 0);
 

@@ -278,3 +278,37 @@ def test_gauss_jordan_final_blocks_against_dense(Nx, Ny, stencil, leaf):
         out = f.run_problem(plan, prob, want_bonds=False)
         compare(out, ref, prob, bonds=False, tol=SYM_TOL if kw.get("symmetric") else TOL,
                 label=f"gj {Nx}x{Ny} {kw}")
+
+
+@pytest.mark.parametrize("Nx,Ny,stencil,leaf", [(16, 16, 5, 2), (12, 10, 5, 2), (9, 14, 5, 2), (8, 8, 5, 1),
+                                                (10, 12, 9, 2), (24, 40, 5, 2)])
+def test_half_leaf_extraction_against_dense(Nx, Ny, stencil, leaf):
+    """Current density from half of the leaves (Sec. 4.3): diagonal and bond
+    outputs of a half-leaf plan against the dense oracle, general and
+    symmetric forms, with energy groups; its bits equal across launch
+    configurations of the final stage it has."""
+    f = find()
+    E = np.array([0.41 + 1e-6j, -2.9 + 1e-6j, 1.3 + 1e-3j])
+    prob = inputs.make_problem(Nx, Ny, stencil, vmax=1.0, seed=Nx * 29 + Ny, energies=E, fL=1.0, fR=0.3)
+    ref = dense.dense_solve(Nx, Ny, stencil, prob["H"], E, prob["sigma"], prob["sigma_less"])
+    for kw in ({}, dict(symmetric=True), dict(streams=2, max_energies=2)):
+        plan = f.Plan(Nx, Ny, stencil, leaf=leaf, half_leaves=True, **kw)
+        tol = SYM_TOL if kw.get("symmetric") else TOL
+        for bonds in (True, False):
+            out = f.run_problem(plan, prob, want_bonds=bonds)
+            compare(out, ref, prob, bonds=bonds, tol=tol, label=f"half {Nx}x{Ny} {kw} bonds={bonds}")
+        opts = plan.tile_options()
+        if any(8 in o for o in opts):
+            plan.set_tiles([8 if 8 in o else 0 for o in opts])
+            out = f.run_problem(plan, prob, want_bonds=False)
+            compare(out, ref, prob, bonds=False, tol=tol, label=f"half gj {Nx}x{Ny} {kw}")
+
+
+def test_half_leaf_extraction_64x64_against_rgf():
+    """64 x 64 with 2 x 2 leaves, 16 energies, bond outputs, half-leaf plan
+    against the RGF oracle."""
+    f = find()
+    prob = inputs.make_preset("c2_64x64")
+    ref = rgf.rgf_solve(64, 64, 5, prob["H"], prob["energies"], prob["sigma"], prob["sigma_less"])
+    out = f.run_problem(f.Plan(64, 64, 5, leaf=2, half_leaves=True, streams=2), prob, want_bonds=True)
+    compare(out, ref, prob, label="half 64x64 leaf 2")

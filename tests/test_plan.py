@@ -380,3 +380,47 @@ def test_solve_rejects_scattering_inputs_for_a_plain_plan():
     plan = find.Plan(6, 6, 5)
     with pytest.raises(ValueError):
         find.solve(plan, None, None, None, None, None, None, sigma_d=object(), sigma_less_d=object())
+
+
+@pytest.mark.parametrize("Nx,Ny,stencil,leaf", [(16, 16, 5, 2), (12, 10, 5, 2), (9, 14, 5, 2), (8, 8, 5, 1),
+                                                (10, 12, 9, 2), (12, 16, 5, 4), (1, 11, 5, 2), (7, 6, 5, 2)])
+@pytest.mark.parametrize("want_bonds", [False, True])
+def test_half_leaf_extraction_matches_oracle(Nx, Ny, stencil, leaf, want_bonds):
+    """Current density from half of the leaves (Sec. 4.3, Fig. cd-opt): the
+    chosen leaves keep the ring around them and output its diagonal and bond
+    entries; every node and bond is output exactly once; the definition-level
+    executor of the plan gives the dense oracle's values.  With 2 x 2 leaves
+    and the 5-point stencil about half of the leaves run the extraction."""
+    from tests.plan_exec import execute
+    find = findlib()
+    E = 0.37 + 1e-3j
+    prob = inputs.make_problem(Nx, Ny, stencil, vmax=0.8, seed=Nx * 11 + Ny, energies=[E], fL=1.0, fR=0.3)
+    p = find.Plan(Nx, Ny, stencil, leaf=leaf, half_leaves=True)
+    full = find.Plan(Nx, Ny, stencil, leaf=leaf)
+    ex = p.export()
+    var = 1 if want_bonds else 0
+    lo = ex["leafout"][ex["leafout"][:, 5] == var]
+    nodes = np.concatenate([ex["outnodes"][r[2]: r[2] + r[1], 0] for r in lo])
+    assert sorted(nodes.tolist()) == list(range(Nx * Ny))           # every node exactly once
+    if want_bonds:
+        bonds = np.concatenate([ex["outbonds"][r[3]: r[3] + r[4], 0] for r in lo])
+        assert sorted(bonds.tolist()) == list(range(inputs.n_bonds(Nx, Ny, stencil)))
+    n_leaves = p.summary()["n_leaves"]
+    if stencil == 5 and leaf == 2 and Nx % 4 == 0 and Ny % 4 == 0:
+        # the checkerboard, plus the skipped leaves on the mesh edge (their
+        # edge-side bond has no chosen neighbour beyond the edge)
+        assert len(lo) <= n_leaves // 2 + Nx // 2 + Ny // 2, (len(lo), n_leaves)
+    Hm = dense.hamiltonian_matrix(Nx, Ny, prob["H"])
+    dG, dL, bG, bL, bJ = execute(ex, Nx, Ny, stencil, Hm, E, prob["sigma"][0], prob["sigma_less"][0], want_bonds)
+    ref = dense.dense_solve(Nx, Ny, stencil, prob["H"], prob["energies"], prob["sigma"], prob["sigma_less"])
+    sc = np.max(np.abs(ref["diag_G"][0]))
+    assert np.max(np.abs(dG - ref["diag_G"][0])) < 1e-11 * sc
+    assert np.max(np.abs(dL - ref["diag_Gless"][0])) < 1e-11 * np.max(np.abs(ref["diag_Gless"][0]))
+    if want_bonds:
+        nb = inputs.n_bonds(Nx, Ny, stencil)
+        g = np.array([bG[k] for k in range(nb)]); l_ = np.array([bL[k] for k in range(nb)])
+        assert np.max(np.abs(g - ref["bond_G"][0])) < 1e-11 * sc
+        assert np.max(np.abs(l_ - ref["bond_Gless"][0])) < 1e-11 * np.max(np.abs(ref["bond_Gless"][0]))
+    # the flop model counts fewer final-stage flops than extracting every leaf
+    if stencil == 5 and leaf <= 2 and Nx * Ny >= 64:
+        assert p.flops_per_energy(want_bonds) < full.flops_per_energy(want_bonds)

@@ -190,6 +190,35 @@ __device__ __forceinline__ void for_each_rc(int nr, int nc, F&& f) {
     for (int r = rr; r < nr; r += rmask + 1) f(r, c);
 }
 
+// Visit (r, c) for r < nr, c < nc, column-major element order dealt to the
+// threads in turn, NB elements per thread per round: the NB values are all
+// fetched (get(r, c), independent loads) before any is consumed
+// (put(r, c, v)), so that gathers from global memory overlap instead of
+// waiting one by one.
+template <int NT, int NBAT, class G, class P>
+__device__ __forceinline__ void gather_rc(int nr, int nc, G&& get, P&& put) {
+  if (nr <= 0 || nc <= 0) return;
+  const int total = nr * nc;
+  const int dc = NT / nr, dr = NT - dc * nr;         // advance of one round step (NT elements)
+  int c0 = int(threadIdx.x) / nr, r0 = int(threadIdx.x) - c0 * nr;
+  for (int e0 = threadIdx.x; e0 < total; e0 += NT * NBAT) {
+    double2 v[NBAT];
+    int rr[NBAT], cc[NBAT];
+    int r = r0, c = c0;
+#pragma unroll
+    for (int u = 0; u < NBAT; ++u) {
+      rr[u] = r; cc[u] = c;
+      v[u] = (e0 + u * NT < total) ? get(r, c) : make_double2(0.0, 0.0);
+      r += dr; c += dc;
+      if (r >= nr) { r -= nr; ++c; }
+    }
+#pragma unroll
+    for (int u = 0; u < NBAT; ++u)
+      if (e0 + u * NT < total) put(rr[u], cc[u], v[u]);
+    r0 = r; c0 = c;
+  }
+}
+
 // C(M x N) <- Cinit - A(M x K) B(K x N), complex.  Each wave computes one
 // (16 TM) x (16 TN) output tile at a time on MFMA (four real products per
 // complex product); operands are fetched PD k-steps ahead of use.  With F32
@@ -763,8 +792,7 @@ __global__ __launch_bounds__(NT, (TC == kTileWg || NT == 512) ? 2 : 3) void k_st
     // 1. assemble the tall block [A_g(S,S); A_g(B,S)]; the other blocks of A_g
     //    and all of Sigma_g are gathered from their sources by the products
     double amax = 0.0;   // this thread's largest |re| + |im| in A_g(S,S)
-    for_each_rc<NT>(na, s, [&](int r, int c) {
-      const double2 v = fr.a(r, c);
+    gather_rc<NT, 8>(na, s, [&](int r, int c) { return fr.a(r, c); }, [&](int r, int c, double2 v) {
       FA[(size_t)c * na + r] = v;
       if (r < s) amax = fmax(amax, fabs(v.x) + fabs(v.y));
     });
@@ -809,13 +837,14 @@ __global__ __launch_bounds__(NT, (TC == kTileWg || NT == 512) ? 2 : 3) void k_st
     };
     // rows and columns of the kept nodes not coupled to S: U and R keep the
     // assembled A_g(B,B) and Sigma_g(B,B) there
-    if (ba < b)
-      for_each_rc<NT>(b, b, [&](int r, int c) {
-        if (r >= ba || c >= ba) {
-          Uo[(size_t)c * b + r] = fr.a(s + r, s + c);
-          if (!E.rzero) Ro[(size_t)c * b + r] = fr.s(s + r, s + c);
-        }
-      });
+    if (ba < b) {
+      auto outside = [=](int r, int c) { return r >= ba || c >= ba; };
+      gather_rc<NT, 8>(b, b, [&](int r, int c) { return outside(r, c) ? fr.a(s + r, s + c) : zero2(); },
+                       [&](int r, int c, double2 v) { if (outside(r, c)) Uo[(size_t)c * b + r] = v; });
+      if (!E.rzero)
+        gather_rc<NT, 8>(b, b, [&](int r, int c) { return outside(r, c) ? fr.s(s + r, s + c) : zero2(); },
+                         [&](int r, int c, double2 v) { if (outside(r, c)) Ro[(size_t)c * b + r] = v; });
+    }
     if (E.f32 == 3) products(std::true_type{}, std::true_type{});
     else if (E.f32 == 2) products(std::false_type{}, std::true_type{});
     else products(std::false_type{}, std::false_type{});
@@ -850,9 +879,10 @@ __global__ __launch_bounds__(NT, 3) void k_final(StageArgs a, OutArgs o) {
     double2* G = pool + E.dst;                    // G(K,K), bp x bp
     for (int k = tid; k < bp; k += NT) L.perm[k] = k;
     double amax = 0.0;   // this thread's largest |re| + |im| in U_K
-    for_each_rc<NT>(n, bp, [&](int r, int c) {
-      const double2 v = r < bp ? Uin[(a.sym & 1) && r < c ? (size_t)r * bp + c : (size_t)c * bp + r]
-                               : make_double2(r - bp == c ? 1.0 : 0.0, 0.0);
+    gather_rc<NT, 8>(n, bp, [&](int r, int c) {
+      return r < bp ? Uin[(a.sym & 1) && r < c ? (size_t)r * bp + c : (size_t)c * bp + r]
+                    : make_double2(r - bp == c ? 1.0 : 0.0, 0.0);
+    }, [&](int r, int c, double2 v) {
       FA[(size_t)c * n + r] = v;
       if (r < bp) amax = fmax(amax, fabs(v.x) + fabs(v.y));
     });

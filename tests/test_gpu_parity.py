@@ -285,6 +285,27 @@ def test_mixed_precision_c2_and_c3_sampled():
     assert np.median(eg) <= 1e-3 and np.median(el) <= 1e-3, (np.median(eg), np.median(el))
 
 
+@pytest.mark.xfail(strict=True, reason="the all-FP32 Schur chain misses 1e-4 near resonances (measured 0.099 max, "
+                   "2.6e-4 median on diag G over the 128x128 grid; one FP64 refinement step on the final blocks "
+                   "does not change it: tests/test_mixed_precision_bound.py)")
+def test_mixed_precision_c3_meets_1e4_contract():
+    """The spec mixed recipe (all Schur products in FP32, FP64 LU, pivots,
+    top levels and final blocks) held to the 1e-4 contract on five energies of
+    the 128 x 128 workload.  Expected to fail; kept strict so that a change
+    that makes it pass is noticed."""
+    f = find()
+    prob = inputs.make_preset("c3_128x128")
+    sample = [0, 64, 128, 192, 255]
+    sub = {k: prob[k][sample] for k in ("energies", "sigma", "sigma_less")}
+    sub["H"] = prob["H"]
+    out = f.run_problem(f.Plan(128, 128, 5, precision=f.PREC_MIXED), sub, want_bonds=False)
+    ref = rgf.rgf_solve(128, 128, 5, prob["H"], sub["energies"], sub["sigma"], sub["sigma_less"], bonds=False)
+    eg = [nrel(out["diag_G"][q], ref["diag_G"][q]) for q in range(len(sample))]
+    el = [nrel(out["diag_Gless"][q], ref["diag_Gless"][q]) for q in range(len(sample))]
+    print("mixed c3 errors: diag G", eg, "diag G<", el)
+    assert max(eg) <= 1e-4 and max(el) <= 1e-4, (max(eg), max(el))
+
+
 GLESS_TOL = 1e-5
 
 

@@ -29,10 +29,10 @@ PRECISION = {"fp64": 0, "mixed": 1, "mixed-gless": 2}   # find_precision values
 # solve, from rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs (calibrated on a
 # plain copy; profiles/elim_kernels_c3_128x128_fp64.md).  Valid only for the
 # native sources (kernels, plan, C-ABI) they were measured on.
-TRAFFIC_BYTES_PER_LAUNCH = 20000807120.13
-TRAFFIC_KERNEL_SHA = "493a9af9fa160391"
-TRAFFIC_TILES = "44551176370111555500"
-TRAFFIC_FORM = (True, 2)   # (symmetric, energy groups) of the counter runs
+TRAFFIC_BYTES_PER_LAUNCH = 19004132559.75
+TRAFFIC_KERNEL_SHA = "9d4c46cbaf360835"
+TRAFFIC_TILES = "44451066360010555800"
+TRAFFIC_FORM = (False, 2)   # (symmetric, energy groups) of the counter runs
 
 
 def native_source_sha() -> str:
@@ -143,6 +143,9 @@ def main() -> int:
     ap.add_argument("--serve-precisions", default="fp64,mixed-gless",
                     help="comma-separated forms served in turn (fp64, mixed, mixed-gless)")
     ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--no-serve-summary", action="store_true",
+                    help="skip the short serving traces (Poisson arrivals at 200 and 4 requests/s, FP64 and the "
+                         "G<-only mixed form) whose p50/p99 latency the benchmark line carries")
     ap.add_argument("--no-graph", action="store_true",
                     help="launch each step eagerly instead of replaying one captured hipGraph")
     ap.add_argument("--complex-mode", choices=["4m", "3m"], default="4m",
@@ -331,6 +334,24 @@ def main() -> int:
                      "plain_find_flops_per_step": plain_flops * nE,
                      "plain_find_equivalent_TFLOPs": plain_flops * nE * args.steps / (kms * 1e9)},
     }
+    if not args.no_serve_summary and args.preset == "c3_128x128" and not args.scattering:
+        # serving: continuous batching of uneven (mesh, energies) requests, p50/p99 latency
+        # beside solves/s, at the configured 200 requests/s and at a rate one GPU sustains
+        import argparse as _ap
+        if not args.no_graph:
+            del graph
+        plan.close()
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        sargs = _ap.Namespace(rates="200,4", rate=200.0, serve_requests=20, serve_precisions="fp64,mixed-gless",
+                              slots=args.slots, symmetric=False)
+        res = serve_bench(sargs)
+        out["serving"] = {
+            "workload": "20 requests per trace, Poisson arrivals, Nx in {32,64,128,256}, Ny in {Nx,2Nx}, "
+                        "5/9-point, 1-64 energies each (seeded), 4 slots, general form",
+            **{form: [{k: r[k] for k in ("rate_req_per_s", "solves_per_s", "p50_latency_s", "p99_latency_s",
+                                         "energy_solves", "max_concurrent")} for r in runs]
+               for form, runs in res.items()}}
     if args.precision != "fp64":
         # error of this result against the FP64 form of the same solve, per energy
         ref = find.Plan(Nx, Ny, st, precision=find.PREC_FP64, scattering=args.scattering)

@@ -141,7 +141,13 @@ typedef enum { FIND_CPLX_4M = 0, FIND_CPLX_3M = 1 } find_complex_mode;
  *                 neighbour reaches; with leaves larger than 2 x 2 the
  *                 interior of a skipped leaf forces it in).  Results are
  *                 those of the default (every leaf); only the work differs.
- *                 0 (default): every leaf. */
+ *                 0 (default): every leaf.
+ *   no_contacts   1: a closed device, A = E I - H (- diag Sigma_d with
+ *                 scattering): no contact self-energies, so the boundary
+ *                 sets follow the stencil alone (the physical boundary of the
+ *                 paper's Table NullBoundaryCost) and sigma / sigma_less may
+ *                 be NULL (they are not read).  0 (default): contacts on the
+ *                 columns y = 0 and y = Ny - 1. */
 typedef struct {
   int leaf;
   int precision;
@@ -153,7 +159,8 @@ typedef struct {
   int streams;
   int scattering;
   int half_leaves;
-  int reserved[3];
+  int no_contacts;
+  int reserved[2];
 } find_plan_opts;
 
 /* Build the cluster tree, boundary sets, gather maps and level schedule for

@@ -383,13 +383,14 @@ find_status find_plan_create(int Nx, int Ny, int stencil, const find_plan_opts* 
   if (o.streams < 0 || o.streams > 4) return fail(FIND_E_ARG, "find_plan_create: streams must be 0..4");
   if (o.scattering != 0 && o.scattering != 1) return fail(FIND_E_ARG, "find_plan_create: scattering must be 0 or 1");
   if (o.half_leaves != 0 && o.half_leaves != 1) return fail(FIND_E_ARG, "find_plan_create: half_leaves must be 0 or 1");
+  if (o.no_contacts != 0 && o.no_contacts != 1) return fail(FIND_E_ARG, "find_plan_create: no_contacts must be 0 or 1");
   if ((long long)Nx * Ny > (1LL << 24)) return fail(FIND_E_UNSUPPORTED, "find_plan_create: mesh larger than 2^24 nodes");
   find_plan_s* p = new (std::nothrow) find_plan_s();
   if (!p) return fail(FIND_E_NOMEM, "find_plan_create: host allocation failed");
   p->opts = o;
   std::string err;
   try {
-    err = build_plan(Nx, Ny, stencil, o.leaf, p->P, o.scattering != 0, o.half_leaves != 0);
+    err = build_plan(Nx, Ny, stencil, o.leaf, p->P, o.scattering != 0, o.half_leaves != 0, o.no_contacts == 0);
   } catch (const std::exception& ex) {
     err = std::string("find_plan_create: ") + ex.what();
   }
@@ -587,8 +588,8 @@ void pass_args(const find_plan_s* plan, const DevState* d, int variant, int e0, 
   a.map_node = d->d_map_node; a.map_srcpos = d->d_map_srcpos;
   a.energies = reinterpret_cast<const double2*>(energies) + e0;
   a.H = H;
-  a.sigma = reinterpret_cast<const double2*>(sigma) + size_t(e0) * 2 * nx2;
-  a.sless = reinterpret_cast<const double2*>(sigma_less) + size_t(e0) * 2 * nx2;
+  a.sigma = sigma ? reinterpret_cast<const double2*>(sigma) + size_t(e0) * 2 * nx2 : nullptr;
+  a.sless = sigma_less ? reinterpret_cast<const double2*>(sigma_less) + size_t(e0) * 2 * nx2 : nullptr;
   a.sscat = sigma_d ? reinterpret_cast<const double2*>(sigma_d) + size_t(e0) * nnodes : nullptr;
   a.slscat = sigma_less_d ? reinterpret_cast<const double2*>(sigma_less_d) + size_t(e0) * nnodes : nullptr;
   a.onsite_off = P.onsite_off;
@@ -597,6 +598,7 @@ void pass_args(const find_plan_s* plan, const DevState* d, int variant, int e0, 
   a.Nx = P.Nx; a.Ny = P.Ny; a.nst = P.stencil == 9 ? 5 : 3;
   a.status = d->status + e0;
   a.sym = sym_bits(plan->opts);
+  a.contacts = P.contacts ? 1 : 0;
   OutArgs o{};
   o.leaves = d->d_leafout[variant];
   o.outnode = d->d_outnode; o.outbond = d->d_outbond; o.H = H;
@@ -752,7 +754,7 @@ find_status find_solve(find_plan plan, int nE, const double* energies, const dou
                        double* bond_Gless, double* bond_J, void* hip_stream) {
   if (!plan) return fail(FIND_E_ARG, "find_solve: NULL plan");
   if (nE < 1) return fail(FIND_E_ARG, "find_solve: nE must be >= 1");
-  if (!energies || !H || !sigma || !sigma_less || !diag_G || !diag_Gless)
+  if (!energies || !H || !diag_G || !diag_Gless || (plan->P.contacts && (!sigma || !sigma_less)))
     return fail(FIND_E_ARG, "find_solve: NULL input or diagonal output pointer");
   if (plan->opts.scattering)
     return fail(FIND_E_ARG, "find_solve: the plan expects scattering self-energies (find_solve_scattering)");
@@ -766,7 +768,8 @@ find_status find_solve_scattering(find_plan plan, int nE, const double* energies
                                   double* bond_G, double* bond_Gless, double* bond_J, void* hip_stream) {
   if (!plan) return fail(FIND_E_ARG, "find_solve_scattering: NULL plan");
   if (nE < 1) return fail(FIND_E_ARG, "find_solve_scattering: nE must be >= 1");
-  if (!energies || !H || !sigma || !sigma_less || !sigma_d || !sigma_less_d || !diag_G || !diag_Gless)
+  if (!energies || !H || !sigma_d || !sigma_less_d || !diag_G || !diag_Gless ||
+      (plan->P.contacts && (!sigma || !sigma_less)))
     return fail(FIND_E_ARG, "find_solve_scattering: NULL input or diagonal output pointer");
   if (!plan->opts.scattering)
     return fail(FIND_E_ARG, "find_solve_scattering: the plan was created without opts.scattering");
@@ -779,7 +782,7 @@ find_status find_solve_noalloc(find_plan plan, int nE, const double* energies, c
                                double* bond_G, double* bond_Gless, double* bond_J, void* hip_stream) {
   if (!plan) return fail(FIND_E_ARG, "find_solve_noalloc: NULL plan");
   if (nE < 1) return fail(FIND_E_ARG, "find_solve_noalloc: nE must be >= 1");
-  if (!energies || !H || !sigma || !sigma_less || !diag_G || !diag_Gless)
+  if (!energies || !H || !diag_G || !diag_Gless || (plan->P.contacts && (!sigma || !sigma_less)))
     return fail(FIND_E_ARG, "find_solve_noalloc: NULL input or diagonal output pointer");
   if (plan->opts.scattering)
     return fail(FIND_E_ARG, "find_solve_noalloc: scattering plans are not supported (use find_solve_scattering)");
@@ -828,7 +831,7 @@ find_status find_plan_autotune(find_plan plan, int nE, const double* energies, c
                                double* diag_Gless, int reps, void* hip_stream) {
   if (!plan) return fail(FIND_E_ARG, "find_plan_autotune: NULL plan");
   if (nE < 1) return fail(FIND_E_ARG, "find_plan_autotune: nE must be >= 1");
-  if (!energies || !H || !sigma || !sigma_less || !diag_G || !diag_Gless)
+  if (!energies || !H || !diag_G || !diag_Gless || (plan->P.contacts && (!sigma || !sigma_less)))
     return fail(FIND_E_ARG, "find_plan_autotune: NULL input or output pointer");
   if (reps < 1) reps = 2;
   std::lock_guard<std::mutex> lk(plan->mu);

@@ -68,6 +68,7 @@ struct Orig {
   const double2* D;     // [2][Ny][Nx] of this energy: E - H_ii - Sigma_d,i, then Sigma<_d,i
   int Nx, Ny, nst;
   int scat;             // 1: diagonal scattering self-energies present (Sigma<_d read from D)
+  int contacts;         // 1: contact self-energies on the columns y = 0 and y = Ny - 1
 
   // H_ij for i = (xi, yi), j = (xj, yj), i != j
   __device__ double hval(int xi, int yi, int xj, int yj) const {
@@ -89,7 +90,7 @@ struct Orig {
     const int dx = xj - xi, dy = yj - yi;
     if (dx == 0 && dy == 0) av = D[yi * Nx + xi];
     else if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) av.x = -hval(xi, yi, xj, yj);
-    if (dy == 0) {
+    if (contacts && dy == 0) {
       if (yi == 0) { const double2 t = sig[xi * Nx + xj]; av.x -= t.x; av.y -= t.y; }
       if (yi == Ny - 1) { const double2 t = sig[Nx * Nx + xi * Nx + xj]; av.x -= t.x; av.y -= t.y; }
     }
@@ -100,7 +101,7 @@ struct Orig {
   __device__ double2 s(int xi, int yi, int xj, int yj) const {
     double2 sv = zero2();
     if (scat && xi == xj && yi == yj) sv = D[Nx * Ny + yi * Nx + xi];
-    if (yi == yj) {
+    if (contacts && yi == yj) {
       if (yi == 0) { const double2 u = sless[xi * Nx + xj]; sv.x += u.x; sv.y += u.y; }
       if (yi == Ny - 1) { const double2 u = sless[Nx * Nx + xi * Nx + xj]; sv.x += u.x; sv.y += u.y; }
     }
@@ -787,8 +788,9 @@ __global__ __launch_bounds__(NT, (TC == kTileWg || NT == 512) ? 2 : 3) void k_st
     for (int k = tid; k < s; k += NT) L.perm[k] = k;
     __syncthreads();
     const Front fr{L.node, L.srcpos, pool + E.src0, pool + E.src1, E.ld0, E.ld1,
-                   Orig{a.H, a.sigma + (size_t)e * 2 * a.Nx * a.Nx, a.sless + (size_t)e * 2 * a.Nx * a.Nx,
-                        pool + a.onsite_off, a.Nx, a.Ny, a.nst, a.sscat != nullptr}, a.sym};
+                   Orig{a.H, a.contacts ? a.sigma + (size_t)e * 2 * a.Nx * a.Nx : nullptr,
+                        a.contacts ? a.sless + (size_t)e * 2 * a.Nx * a.Nx : nullptr,
+                        pool + a.onsite_off, a.Nx, a.Ny, a.nst, a.sscat != nullptr, a.contacts}, a.sym};
     // 1. assemble the tall block [A_g(S,S); A_g(B,S)]; the other blocks of A_g
     //    and all of Sigma_g are gathered from their sources by the products
     double amax = 0.0;   // this thread's largest |re| + |im| in A_g(S,S)

@@ -42,6 +42,7 @@ struct StageArgs {
   int Nx, Ny, nst;
   int* status;            // per energy of this pass: 1 = zero or tiny pivot met
   int sym;                // bit 0: U complex symmetric (lower half formed); R is always formed whole
+  int contacts;           // 1: contact self-energies on the columns y = 0 and y = Ny - 1 (sigma, sless read)
 };
 
 struct OutArgs {

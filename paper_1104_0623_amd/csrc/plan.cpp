@@ -133,10 +133,11 @@ struct Builder {
           });
           // dense contact blocks couple every pair of nodes on a contact column
           bool full_col = (r.x0 == 0 && r.w == Nx);
-          if ((y == 0 || y == Ny - 1) && !full_col) bnd = true;
+          if (P.contacts && (y == 0 || y == Ny - 1) && !full_col) bnd = true;
           if (bnd) B.push_back(y * Nx + x);
         }
       for (int cy : {0, Ny - 1}) {
+        if (!P.contacts) break;
         if (cy < r.y0 || cy >= r.y0 + r.h) continue;  // C does not touch this contact column
         for (int x = 0; x < Nx; ++x) {
           if (x >= r.x0 && x < r.x0 + r.w) continue;
@@ -162,7 +163,9 @@ struct Builder {
   // Sigma<(C, C) = 0, and so R = 0 for it and (recursively) for all its
   // descendants
   // (with diagonal scattering self-energies every node carries Sigma<, and no R vanishes)
-  bool up_rzero(const Cluster& c) const { return !P.scattering && c.r.y0 > 0 && c.r.y0 + c.r.h < Ny; }
+  bool up_rzero(const Cluster& c) const {
+    return !P.scattering && (!P.contacts || (c.r.y0 > 0 && c.r.y0 + c.r.h < Ny));
+  }
 
   // Emit an elimination whose assembled node list is `list` (with per-entry
   // source and source position) and whose kept set is `keep` (in this order).
@@ -193,7 +196,7 @@ struct Builder {
     auto carries = [&](int k) -> bool {
       if (src[k] == SRC0 || src[k] == SRC1) return sig_src[src[k]] && (*sig_src[src[k]])[pos[k]];
       const int y = list[k] / Nx;
-      return P.scattering || y == 0 || y == Ny - 1;
+      return P.scattering || (P.contacts && (y == 0 || y == Ny - 1));
     };
     const auto mid = std::stable_partition(S_idx.begin(), S_idx.end(), carries);
     e.ssig = e.rzero ? 0 : int(mid - S_idx.begin());
@@ -223,7 +226,7 @@ struct Builder {
           const int xs = list[ks] % Nx, ys = list[ks] / Nx;
           const int dx = std::abs(xs - xb), dy = std::abs(ys - yb);
           if (dx <= 1 && dy <= 1 && (dx + dy == 1 || (stencil == 9 && dx + dy == 2))) return true;
-          if (ys == yb && (ys == 0 || ys == Ny - 1)) return true;
+          if (P.contacts && ys == yb && (ys == 0 || ys == Ny - 1)) return true;
         }
         return false;
       };
@@ -531,10 +534,12 @@ struct Builder {
 
 }  // namespace
 
-std::string build_plan(int Nx, int Ny, int stencil, int leaf, Plan& P, bool scattering, bool half_leaves) {
+std::string build_plan(int Nx, int Ny, int stencil, int leaf, Plan& P, bool scattering, bool half_leaves,
+                       bool contacts) {
   P = Plan();
   P.Nx = Nx; P.Ny = Ny; P.stencil = stencil; P.leaf = leaf; P.scattering = scattering;
   P.half_leaves = half_leaves;
+  P.contacts = contacts;
   Builder b(P);
   return b.build();
 }

@@ -60,6 +60,9 @@ struct Plan {
   // leaf extraction on a checkerboard of leaves whose kept sets cover the ring
   // around them (current density from half of the leaves)
   bool half_leaves = false;
+  // contact self-energies on the columns y = 0 and y = Ny - 1 (false: a closed
+  // device, A = E I - H, no contact coupling in the sets)
+  bool contacts = true;
   // pool offset (per energy) of the node diagonal: A_ii of the original matrix
   // without its contact part (E - H_ii - Sigma_d,i), then Sigma<_d,i ([2][Ny][Nx])
   int64_t onsite_off = 0;
@@ -81,7 +84,7 @@ struct Plan {
 int count_bonds(int Nx, int Ny, int stencil);
 // Builds the plan; returns an empty string on success, else a message.
 std::string build_plan(int Nx, int Ny, int stencil, int leaf, Plan& P, bool scattering = false,
-                       bool half_leaves = false);
+                       bool half_leaves = false, bool contacts = true);
 // sym: bit 0 = only half of U formed, bit 1 = only half of R formed
 double elim_flops(const Elim& e, int sym = 0);
 

@@ -37,7 +37,8 @@ class PlanOpts(ctypes.Structure):
     _fields_ = [("leaf", ctypes.c_int), ("precision", ctypes.c_int), ("max_energies", ctypes.c_int),
                 ("fp64_top_levels", ctypes.c_int), ("workspace_budget", ctypes.c_size_t),
                 ("complex_mode", ctypes.c_int), ("symmetric", ctypes.c_int), ("streams", ctypes.c_int),
-                ("scattering", ctypes.c_int), ("half_leaves", ctypes.c_int), ("reserved", ctypes.c_int * 3)]
+                ("scattering", ctypes.c_int), ("half_leaves", ctypes.c_int), ("no_contacts", ctypes.c_int),
+                ("reserved", ctypes.c_int * 2)]
 
 
 class PlanSummary(ctypes.Structure):
@@ -108,14 +109,15 @@ class Plan:
     def __init__(self, Nx: int, Ny: int, stencil: int = 5, leaf: int = 8, precision: int = PREC_FP64,
                  max_energies: int = 0, workspace_budget: int = 0, fp64_top_levels: int = 0,
                  complex_mode: int = CPLX_4M, symmetric: bool = False, streams: int = 0,
-                 scattering: bool = False, half_leaves: bool = False):
+                 scattering: bool = False, half_leaves: bool = False, no_contacts: bool = False):
         self.Nx, self.Ny, self.stencil = Nx, Ny, stencil
         self.scattering = bool(scattering)
         self._h = ctypes.c_void_p()
         o = PlanOpts(leaf=leaf, precision=precision, max_energies=max_energies,
                      workspace_budget=workspace_budget, fp64_top_levels=fp64_top_levels,
                      complex_mode=complex_mode, symmetric=int(bool(symmetric)), streams=streams,
-                     scattering=int(bool(scattering)), half_leaves=int(bool(half_leaves)))
+                     scattering=int(bool(scattering)), half_leaves=int(bool(half_leaves)),
+                     no_contacts=int(bool(no_contacts)))
         _check(lib().find_plan_create(Nx, Ny, stencil, ctypes.byref(o), ctypes.byref(self._h)))
 
     def close(self):

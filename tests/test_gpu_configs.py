@@ -312,3 +312,29 @@ def test_half_leaf_extraction_64x64_against_rgf():
     ref = rgf.rgf_solve(64, 64, 5, prob["H"], prob["energies"], prob["sigma"], prob["sigma_less"])
     out = f.run_problem(f.Plan(64, 64, 5, leaf=2, half_leaves=True, streams=2), prob, want_bonds=True)
     compare(out, ref, prob, label="half 64x64 leaf 2")
+
+
+@pytest.mark.parametrize("Nx,Ny,stencil,leaf", [(16, 16, 5, 4), (12, 9, 9, 4), (24, 40, 5, 8)])
+def test_closed_device_against_dense(Nx, Ny, stencil, leaf):
+    """A plan without contacts (no_contacts): A = E I - H, sigma pointers NULL;
+    with diagonal scattering self-energies G< is non-zero.  Against the dense
+    oracle with zero contact self-energies."""
+    import torch
+    f = find()
+    E = np.array([0.41 + 1e-3j, -2.9 + 1e-6j, 1.3 + 1e-2j])
+    prob = inputs.make_problem(Nx, Ny, stencil, vmax=1.0, seed=Nx * 37 + Ny, energies=E, fL=1.0, fR=0.3)
+    zero = np.zeros_like(prob["sigma"])
+    sd, sl = inputs.scattering_self_energies_varied(Nx, Ny, E.size, gamma=0.05, shift=0.05, seed=Nx)
+    ref = dense.dense_solve(Nx, Ny, stencil, prob["H"], E, zero, zero, sigma_d=sd, sigma_less_d=sl)
+    dev = torch.device("cuda")
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), device=dev)
+    nb = f.n_bonds(Nx, Ny, stencil)
+    for kw in ({}, dict(symmetric=True), dict(streams=2, max_energies=2)):
+        plan = f.Plan(Nx, Ny, stencil, leaf=leaf, scattering=True, no_contacts=True, **kw)
+        outs = [torch.zeros((E.size, Ny, Nx), dtype=torch.complex128, device=dev) for _ in range(2)] + \
+               [torch.zeros((E.size, nb), dtype=torch.complex128, device=dev) for _ in range(2)] + \
+               [torch.zeros((E.size, nb), dtype=torch.float64, device=dev)]
+        f.solve(plan, t(E), t(prob["H"]), None, None, *outs, sigma_d=t(sd), sigma_less_d=t(sl))
+        f.sync_status(plan)
+        out = dict(zip(("diag_G", "diag_Gless", "bond_G", "bond_Gless", "bond_J"), (o.cpu().numpy() for o in outs)))
+        compare(out, ref, prob, tol=SYM_TOL if kw.get("symmetric") else TOL, label=f"closed {Nx}x{Ny} {kw}")

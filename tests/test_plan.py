@@ -424,3 +424,38 @@ def test_half_leaf_extraction_matches_oracle(Nx, Ny, stencil, leaf, want_bonds):
     # the flop model counts fewer final-stage flops than extracting every leaf
     if stencil == 5 and leaf <= 2 and Nx * Ny >= 64:
         assert p.flops_per_energy(want_bonds) < full.flops_per_energy(want_bonds)
+
+
+def test_closed_device_plan_matches_table_null_boundary_cost():
+    """Table NullBoundaryCost (appendix; Sec. 4.4 for the physical boundary):
+    for an N x N 5-point mesh with no contacts, per tree level (root = level
+    0), the summed cost s^3/3 + s^2 b + s b^2 of the upward and downward
+    eliminations in units of N^3.  The table is exact for the large clusters
+    near the root (levels 1-4) and an estimate that ignores the physical
+    boundary for the smaller ones, so the plan's levels 1-4 must match within
+    15% and its levels 5 and 6 may not exceed the table's."""
+    find = findlib()
+    N = 256
+    up_tab = {1: 4.666, 2: 9.332, 3: 2.040 + 4.540, 4: 3.168 + 4.080 + 1.168,
+              5: 0.2552 + 0.3958 + 1.703 + 2.312, 6: 6.336}
+    dn_tab = {2: 9.332, 3: 14.624 + 4.540, 4: 4.332 + 2.040 + 14.624 + 9.332, 5: 52.672, 6: 38.976}
+    el = find.Plan(N, N, 5, no_contacts=True).export()["elims"]
+    up, dn = {}, {}
+    for r in el:
+        if r[0] != 0 or r[11] not in (0, 1):
+            continue
+        s, b = r[1] / N, r[2] / N
+        d = up if r[11] == 0 else dn
+        d[int(r[12])] = d.get(int(r[12]), 0.0) + s ** 3 / 3 + s * s * b + s * b * b
+    assert dn.get(1, 0.0) == 0.0                       # level 1: the root's halves eliminate nothing
+    for tab, got in ((up_tab, up), (dn_tab, dn)):
+        for lev, c in tab.items():
+            if lev <= 4:
+                assert abs(got[lev] - c) <= 0.15 * c, (lev, got[lev], c)
+            else:
+                assert got[lev] <= c, (lev, got[lev], c)
+    # with contacts the contact columns join the boundary sets: more work
+    with_contacts = find.Plan(N, N, 5).export()["elims"]
+    cost = lambda E: sum(float(r[1]) ** 3 / 3 + float(r[1]) ** 2 * r[2] + float(r[1]) * float(r[2]) ** 2
+                         for r in E if r[0] == 0)
+    assert cost(with_contacts) > cost(el)

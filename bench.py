@@ -32,7 +32,7 @@ PRECISION = {"fp64": 0, "mixed": 1, "mixed-gless": 2}   # find_precision values
 TRAFFIC_BYTES_PER_LAUNCH = 19004132559.75
 TRAFFIC_KERNEL_SHA = "9d4c46cbaf360835"
 TRAFFIC_TILES = "44451066360010555800"
-TRAFFIC_FORM = (False, 2)   # (symmetric, energy groups) of the counter runs
+TRAFFIC_FORM = (0, 2)   # (symmetric form, energy groups) of the counter runs
 
 
 def native_source_sha() -> str:
@@ -152,10 +152,11 @@ def main() -> int:
                     help="real split of the complex Schur products")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default wave tile (32x32) for every stage instead of tuning it")
-    ap.add_argument("--symmetric", action="store_true",
-                    help="assert that A is complex symmetric (true for these inputs) and form only the lower "
-                         "half of each U; by default the general form runs (it keeps the 1e-10 accuracy at the "
-                         "ill-conditioned energies where the mirrored U loses a factor of a few)")
+    ap.add_argument("--symmetric", type=int, nargs="?", const=1, default=0, choices=[0, 1, 2],
+                    help="assert that A is complex symmetric (true for these inputs): 1 forms and stores only "
+                         "the lower half of each U, 2 also of each R (about half the energy pool; G< loses "
+                         "accuracy near resonances).  By default the general form runs (it keeps the 1e-10 "
+                         "accuracy at the ill-conditioned energies where the mirrored U loses a factor of a few)")
     ap.add_argument("--streams", type=int, default=2, help="energy groups solved concurrently (0/1 = one)")
     ap.add_argument("--bonds", action="store_true",
                     help="also return G and G< on every bond and the bond currents (the leaf extraction "
@@ -220,7 +221,8 @@ def main() -> int:
     stream = torch.cuda.Stream()          # non-default stream (graph capture needs one)
     torch.cuda.set_stream(stream)
     tune_s = 0.0
-    key = f"{Nx}x{Ny}/{st}/{args.leaf}/{args.precision}/{args.complex_mode}" + ("/sym" if args.symmetric else "")
+    key = f"{Nx}x{Ny}/{st}/{args.leaf}/{args.precision}/{args.complex_mode}" + \
+        {0: "", 1: "/sym", 2: "/sym2"}[args.symmetric]
     table = json.load(open(os.path.join(ROOT, "paper_1104_0623_amd", "tuning.json")))
     tiles_from = "autotune"
     if args.scattering:
@@ -315,6 +317,7 @@ def main() -> int:
                    "half_leaves": bool(args.half_leaves),
                    "Nx": Nx, "Ny": Ny, "stencil": st, "energies_per_step": nE, "precision": args.precision,
                    "leaf": args.leaf, "complex_mode": args.complex_mode, "symmetric": args.symmetric, "streams": args.streams,
+                   "pool_MB_per_energy": round(plan.summary()["pool_per_energy"] * 16 / 1e6, 2),
                    "launch": "eager" if args.no_graph else "hipGraph replay per batch",
                    "stage_tiles": "".join(str(t) for t in tiles),
                    "stage_tiles_from": tiles_from,

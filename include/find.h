@@ -102,21 +102,28 @@ typedef enum { FIND_CPLX_4M = 0, FIND_CPLX_3M = 1 } find_complex_mode;
  *                 (ar + ai)(br + bi)).  3M rounds differently, within the
  *                 same tolerances; flop counts stay at 8 per complex
  *                 multiply-add either way.
- *   symmetric     1 asserts that A is complex symmetric (H real symmetric,
- *                 Sigma_L and Sigma_R complex symmetric, as for leads with a
- *                 real transverse basis).  Every Schur complement U is then
- *                 complex symmetric (Prop. 1 of the paper), so only its lower
- *                 triangle is formed and readers take the upper entries from
- *                 their mirrors (s b^2 / 2 fewer complex multiply-adds per
- *                 elimination; the flop model of find_plan_flops follows).
- *                 R (anti-Hermitian when Sigma< is) is formed whole: the two
- *                 computed triangles round differently, and mirroring one of
- *                 them amplifies the rounding of G< by orders of magnitude at
- *                 energies near resonances.  The mirrored U itself costs a
- *                 factor of a few in accuracy at ill-conditioned energies
- *                 (errors up to ~5e-10 where the general form has 1e-10), so
- *                 the general form is the accurate default.  Inputs that break
- *                 the assertion give wrong results.  0 (default) = general.
+ *   symmetric     1 or 2 asserts that A is complex symmetric (H real
+ *                 symmetric, Sigma_L and Sigma_R complex symmetric, as for
+ *                 leads with a real transverse basis).  Every Schur
+ *                 complement U is then complex symmetric (Prop. 1 of the
+ *                 paper): with 1, only its lower triangle is formed and it is
+ *                 stored packed by columns (column c holds rows c..b-1), and
+ *                 readers take an upper entry from its mirror (s b^2 / 2
+ *                 fewer complex multiply-adds per elimination; the flop model
+ *                 of find_plan_flops follows).  R (anti-Hermitian when Sigma<
+ *                 is) is then formed and stored whole.  With 2, R is halved
+ *                 the same way (an upper entry read as minus the conjugate of
+ *                 its mirror), so that the energy pool is about half that of
+ *                 the general form (storage reduction of the symmetric U, and
+ *                 of the anti-Hermitian R); the two computed triangles of R
+ *                 round differently, and the mirrored R amplifies the rounding
+ *                 of G< = G R G^dagger at energies near resonances (diag G<
+ *                 relative errors up to ~1e-7 against ~1e-12, G unaffected).
+ *                 The mirrored U itself costs a factor of a few in accuracy at
+ *                 ill-conditioned energies (errors up to ~5e-10 where the
+ *                 general form has 1e-10), so the general form is the
+ *                 accurate default.  Inputs that break the assertion give
+ *                 wrong results.  0 (default) = general, U and R whole.
  *   streams       energy groups solved concurrently inside one pass (0 or 1
  *                 = one, on the caller's stream; 2..4 = that many groups, each
  *                 on a stream of the plan, forked from and joined back to the
@@ -332,7 +339,8 @@ enum {
   FIND_EF_KIND = 0,    /* 0 = Schur elimination, 1 = final leaf block           */
   FIND_EF_S, FIND_EF_B, FIND_EF_N,
   FIND_EF_SRC0, FIND_EF_LD0, FIND_EF_SRC1, FIND_EF_LD1, /* pool offsets (complex), -1 = none */
-  FIND_EF_DST,         /* pool offset of U (b x b); R follows at DST + b*b     */
+  FIND_EF_DST,         /* pool offset of U (b x b); R follows at DST + b*b, or  */
+                       /* at DST + b(b+1)/2 with U packed (symmetric forms)    */
   FIND_EF_MAP,         /* first entry of this elimination's map (n entries)    */
   FIND_EF_CLUSTER, FIND_EF_PHASE, FIND_EF_LEVEL,
   FIND_EF_RZERO,       /* 1: Sigma< vanishes on the front, so R = 0 (not formed) */

@@ -180,12 +180,14 @@ find_status upload(T** dptr, const std::vector<T>& h, size_t& bytes) {
   return FIND_OK;
 }
 
-// Halved triangle of the symmetric form: bit 0 = U (complex symmetric, Prop. 1
-// of the paper).  R, although anti-Hermitian, is formed whole: the rounding of
-// its two computed triangles differs, and replacing one by the mirror of the
-// other amplifies the rounding of G< = G R G^dagger by orders of magnitude at
+// Halved triangles of the symmetric forms, formed and stored as packed lower
+// triangles: bit 0 = U (complex symmetric, Prop. 1 of the paper), with
+// symmetric = 1 or 2; bit 1 = R (anti-Hermitian), with symmetric = 2 only.
+// With symmetric = 1, R is formed and stored whole: the rounding of its two
+// computed triangles differs, and replacing one by the mirror of the other
+// amplifies the rounding of G< = G R G^dagger by orders of magnitude at
 // energies near resonances of the device (where G is large).
-int sym_bits(const find_plan_opts& o) { return o.symmetric ? 1 : 0; }
+int sym_bits(const find_plan_opts& o) { return o.symmetric == 0 ? 0 : o.symmetric == 1 ? 1 : 3; }
 
 // Workspace (complex elements) of one Schur elimination: the tall block
 // [A(S,S); A(B,S)] (n x s), L (b x s) and W_q (b x ssig).
@@ -379,7 +381,7 @@ find_status find_plan_create(int Nx, int Ny, int stencil, const find_plan_opts* 
   if (o.max_energies < 0) return fail(FIND_E_ARG, "find_plan_create: max_energies must be >= 0");
   if (o.complex_mode != FIND_CPLX_4M && o.complex_mode != FIND_CPLX_3M)
     return fail(FIND_E_ARG, "find_plan_create: unknown complex_mode");
-  if (o.symmetric != 0 && o.symmetric != 1) return fail(FIND_E_ARG, "find_plan_create: symmetric must be 0 or 1");
+  if (o.symmetric < 0 || o.symmetric > 2) return fail(FIND_E_ARG, "find_plan_create: symmetric must be 0, 1 or 2");
   if (o.streams < 0 || o.streams > 4) return fail(FIND_E_ARG, "find_plan_create: streams must be 0..4");
   if (o.scattering != 0 && o.scattering != 1) return fail(FIND_E_ARG, "find_plan_create: scattering must be 0 or 1");
   if (o.half_leaves != 0 && o.half_leaves != 1) return fail(FIND_E_ARG, "find_plan_create: half_leaves must be 0 or 1");
@@ -390,7 +392,8 @@ find_status find_plan_create(int Nx, int Ny, int stencil, const find_plan_opts* 
   p->opts = o;
   std::string err;
   try {
-    err = build_plan(Nx, Ny, stencil, o.leaf, p->P, o.scattering != 0, o.half_leaves != 0, o.no_contacts == 0);
+    err = build_plan(Nx, Ny, stencil, o.leaf, p->P, o.scattering != 0, o.half_leaves != 0, o.no_contacts == 0,
+                     sym_bits(o));
   } catch (const std::exception& ex) {
     err = std::string("find_plan_create: ") + ex.what();
   }

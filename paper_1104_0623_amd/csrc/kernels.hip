@@ -137,6 +137,33 @@ struct LdsT {
 template <class LDS>
 constexpr bool has_wg() { return std::is_same<decltype(LDS::wg), WgLds>::value; }
 
+// Stored b x b blocks of the pool: whole (column-major, ld b), or, in the
+// symmetric forms, the lower triangle packed by columns (column c holds rows
+// c .. b - 1 and starts at c b - c (c - 1) / 2).  U (complex symmetric) reads
+// an upper entry as its mirror, R (anti-Hermitian) as minus the conjugate of
+// its mirror.  R follows U in its slot.
+__device__ __forceinline__ size_t tri_off(int r, int c, int b) {
+  return (size_t)c * b - (((size_t)c * (c - 1)) >> 1) + (r - c);
+}
+__device__ __forceinline__ size_t block_size(int b, bool packed) {
+  return packed ? ((size_t)b * (b + 1)) >> 1 : (size_t)b * b;
+}
+__device__ __forceinline__ double2 read_u(const double2* U, int b, int r, int c, bool packed) {
+  if (!packed) return U[(size_t)c * b + r];
+  return r >= c ? U[tri_off(r, c, b)] : U[tri_off(c, r, b)];
+}
+__device__ __forceinline__ double2 read_r(const double2* R, int b, int r, int c, bool packed) {
+  if (!packed) return R[(size_t)c * b + r];
+  if (r >= c) return R[tri_off(r, c, b)];
+  const double2 v = R[tri_off(c, r, b)];
+  return make_double2(-v.x, v.y);
+}
+// store of entry (r, c) of a formed block; with a packed block only r >= c is kept
+__device__ __forceinline__ void write_blk(double2* X, int b, int r, int c, bool packed, double2 v) {
+  if (!packed) X[(size_t)c * b + r] = v;
+  else if (r >= c) X[tri_off(r, c, b)] = v;
+}
+
 // Entries of the assembled front A_g / Sigma_g of one elimination, by front
 // row/column (local [S ; B] index): the block of a source cluster's stored U
 // (or R) when both indices come from that source, else the original A (or
@@ -148,18 +175,13 @@ struct Front {
   const double2* U1;
   int ld0, ld1;
   Orig o;
-  int sym;             // bit 0: sources hold only the lower triangle of U (= U^T)
+  int sym;             // bit 0: sources hold U as a packed lower triangle, bit 1: R likewise
 
   __device__ double2 a(int r, int c) const {
     const int spr = srcpos[r], spc = srcpos[c];
     const int sr = spr >> 24;
-    if (sr == (spc >> 24) && sr < 2) {
-      const double2* U = sr ? U1 : U0;
-      const int ld = sr ? ld1 : ld0;
-      int pr = spr & 0xffffff, pc = spc & 0xffffff;
-      if ((sym & 1) && pr < pc) { const int t = pr; pr = pc; pc = t; }
-      return U[(size_t)pc * ld + pr];
-    }
+    if (sr == (spc >> 24) && sr < 2)
+      return read_u(sr ? U1 : U0, sr ? ld1 : ld0, spr & 0xffffff, spc & 0xffffff, sym & 1);
     const int gr = node[r], gc = node[c];
     return o.a(gr & 0xffff, gr >> 16, gc & 0xffff, gc >> 16);
   }
@@ -168,9 +190,8 @@ struct Front {
     const int sr = spr >> 24;
     if (sr == (spc >> 24) && sr < 2) {
       const int ld = sr ? ld1 : ld0;
-      const double2* R = (sr ? U1 : U0) + (size_t)ld * ld;
-      const int pr = spr & 0xffffff, pc = spc & 0xffffff;
-      return R[(size_t)pc * ld + pr];
+      const double2* R = (sr ? U1 : U0) + block_size(ld, sym & 1);
+      return read_r(R, ld, spr & 0xffffff, spc & 0xffffff, sym & 2);
     }
     const int gr = node[r], gc = node[c];
     return o.s(gr & 0xffff, gr >> 16, gc & 0xffff, gc >> 16);
@@ -806,13 +827,15 @@ __global__ __launch_bounds__(NT, (TC == kTileWg || NT == 512) ? 2 : 3) void k_st
     }
     // 4. U = A(B,B) - L A(S,B); 5. W_q and R (FP32 products in the mixed form,
     // FP64 otherwise)
+    // U and R of this front, whole or as packed lower triangles
+    const bool pu = a.sym & 1, pr = a.sym & 2;
     double2* Uo = pool + E.dst;
-    double2* Ro = Uo + (size_t)b * b;
+    double2* Ro = Uo + block_size(b, pu);
     const int q = E.ssig, q0 = E.bsig ? E.ssig : 0;
     auto lo_ = [=](int r, int k) { return Lo[(size_t)k * ba + r]; };
     auto bu = [=](int k, int c) { return fr.a(k, s + c); };
     auto cu = [=](int r, int c) { return fr.a(s + r, s + c); };
-    auto su = [=](int r, int c, double2 v) { Uo[(size_t)c * b + r] = v; };
+    auto su = [=](int r, int c, double2 v) { write_blk(Uo, b, r, c, pu, v); };
     auto bw = [=](int k, int c) { return fr.s(k, c); };
     auto cw = [=](int r, int c) { return fr.s(s + r, c); };
     auto sw = [=](int r, int c, double2 v) { W[(size_t)c * ba + r] = v; };
@@ -820,32 +843,33 @@ __global__ __launch_bounds__(NT, (TC == kTileWg || NT == 512) ? 2 : 3) void k_st
     auto ar = [=](int r, int k) { return k < q0 ? Lo[(size_t)k * ba + r] : W[(size_t)(k - q0) * ba + r]; };
     auto br = [=](int k, int c) { return k < q0 ? fr.s(k, s + c) : conjd(Lo[(size_t)(k - q0) * ba + c]); };
     auto cr = [=](int r, int c) { return fr.s(s + r, s + c); };
-    auto sr = [=](int r, int c, double2 v) { Ro[(size_t)c * b + r] = v; };
-    // with a.sym, U is complex symmetric: its tiles above the diagonal are not
-    // formed, and every reader of U takes an upper entry from its mirror below
-    // the diagonal (R is formed whole)
-    const int tri = (a.sym & 1) ? ba : 0;
+    auto sr = [=](int r, int c, double2 v) { write_blk(Ro, b, r, c, pr, v); };
+    // in the symmetric forms U (complex symmetric), and with sym bit 1 also R
+    // (anti-Hermitian), is formed and stored as its lower triangle: tiles above
+    // the diagonal are not formed, and readers take an upper entry from its
+    // mirror below the diagonal
+    const int tri = pu ? ba : 0, trir = pr ? ba : 0;
     auto products = [&](auto fu, auto fs) {
       constexpr bool FU = decltype(fu)::value, FS = decltype(fs)::value;
       gemm_schur<NT, FU, TC, CM == 1>(L, ba, ba, s, tri, lo_, bu, cu, su);
       if (E.rzero) {
         // Sigma< vanishes on this front: R = 0
-        for_each_rc<NT>(b, b, [&](int r, int c) { Ro[(size_t)c * b + r] = zero2(); });
+        for_each_rc<NT>(b, b, [&](int r, int c) { write_blk(Ro, b, r, c, pr, zero2()); });
       } else {
         if (q > 0) gemm_schur<NT, FS, TC, CM == 1>(L, ba, q, q, 0, lo_, bw, cw, sw);
         __syncthreads();
-        gemm_schur<NT, FS, TC, CM == 1>(L, ba, ba, q0 + q, 0, ar, br, cr, sr);
+        gemm_schur<NT, FS, TC, CM == 1>(L, ba, ba, q0 + q, trir, ar, br, cr, sr);
       }
     };
     // rows and columns of the kept nodes not coupled to S: U and R keep the
     // assembled A_g(B,B) and Sigma_g(B,B) there
     if (ba < b) {
-      auto outside = [=](int r, int c) { return r >= ba || c >= ba; };
-      gather_rc<NT, 8>(b, b, [&](int r, int c) { return outside(r, c) ? fr.a(s + r, s + c) : zero2(); },
-                       [&](int r, int c, double2 v) { if (outside(r, c)) Uo[(size_t)c * b + r] = v; });
+      auto outside = [=](int r, int c, bool packed) { return (r >= ba || c >= ba) && (!packed || r >= c); };
+      gather_rc<NT, 8>(b, b, [&](int r, int c) { return outside(r, c, pu) ? fr.a(s + r, s + c) : zero2(); },
+                       [&](int r, int c, double2 v) { if (outside(r, c, pu)) write_blk(Uo, b, r, c, pu, v); });
       if (!E.rzero)
-        gather_rc<NT, 8>(b, b, [&](int r, int c) { return outside(r, c) ? fr.s(s + r, s + c) : zero2(); },
-                         [&](int r, int c, double2 v) { if (outside(r, c)) Ro[(size_t)c * b + r] = v; });
+        gather_rc<NT, 8>(b, b, [&](int r, int c) { return outside(r, c, pr) ? fr.s(s + r, s + c) : zero2(); },
+                         [&](int r, int c, double2 v) { if (outside(r, c, pr)) write_blk(Ro, b, r, c, pr, v); });
     }
     if (E.f32 == 3) products(std::true_type{}, std::true_type{});
     else if (E.f32 == 2) products(std::false_type{}, std::true_type{});
@@ -876,13 +900,14 @@ __global__ __launch_bounds__(NT, 3) void k_final(StageArgs a, OutArgs o) {
     const int bp = E.b, n = 2 * bp;
     double2* T = FA + (size_t)n * bp;             // bp x bp
     double2* pool = a.pool + (size_t)e * a.pool_stride;
-    const double2* Uin = pool + E.src0;           // U_K, ld bp
-    const double2* Rin = Uin + (size_t)bp * bp;   // R_K
+    const bool pu = a.sym & 1, pr = a.sym & 2;
+    const double2* Uin = pool + E.src0;             // U_K (bp x bp, whole or packed)
+    const double2* Rin = Uin + block_size(bp, pu);  // R_K
     double2* G = pool + E.dst;                    // G(K,K), bp x bp
     for (int k = tid; k < bp; k += NT) L.perm[k] = k;
     double amax = 0.0;   // this thread's largest |re| + |im| in U_K
     gather_rc<NT, 8>(n, bp, [&](int r, int c) {
-      return r < bp ? Uin[(a.sym & 1) && r < c ? (size_t)r * bp + c : (size_t)c * bp + r]
+      return r < bp ? read_u(Uin, bp, r, c, pu)
                     : make_double2(r - bp == c ? 1.0 : 0.0, 0.0);
     }, [&](int r, int c, double2 v) {
       FA[(size_t)c * n + r] = v;
@@ -896,7 +921,7 @@ __global__ __launch_bounds__(NT, 3) void k_final(StageArgs a, OutArgs o) {
     // its first rs rows and columns, so T has rs rows and the sum runs over rs
     const int rs = E.ssig;
     gemm_sub<NT>(rs, bp, rs,
-             [=](int r, int k) { return Rin[(size_t)k * bp + r]; },
+             [=](int r, int k) { return read_r(Rin, bp, r, k, pr); },
              [=](int k, int c) { return conjd(G[(size_t)k * bp + c]); },
              [=](int r, int c) { return zero2(); },
              [=](int r, int c, double2 v) { T[(size_t)c * bp + r] = make_double2(-v.x, -v.y); });
@@ -978,8 +1003,9 @@ __global__ __launch_bounds__(NT, 3) void k_final_gj(StageArgs a, OutArgs o) {
     const ElimDev E = a.elims[ei];
     const LeafOutDev Lo = o.leaves[E.aux];
     const int bp = E.b, rs = E.ssig;
-    const double2* Uin = a.pool + (size_t)e * a.pool_stride + E.src0;   // U_K, ld bp
-    const double2* Rin = Uin + (size_t)bp * bp;                            // R_K
+    const bool pu = a.sym & 1, pr = a.sym & 2;
+    const double2* Uin = a.pool + (size_t)e * a.pool_stride + E.src0;   // U_K (whole or packed)
+    const double2* Rin = Uin + block_size(bp, pu);                         // R_K
     double2 M[4][4];
     double amax = 0.0;
 #pragma unroll
@@ -989,14 +1015,14 @@ __global__ __launch_bounds__(NT, 3) void k_final_gj(StageArgs a, OutArgs o) {
         const int r = 4 * rb + i, c = 4 * cb + j;
         double2 v = make_double2(r == c ? 1.0 : 0.0, 0.0);
         if (r < bp && c < bp) {
-          v = Uin[(a.sym & 1) && r < c ? (size_t)r * bp + c : (size_t)c * bp + r];
+          v = read_u(Uin, bp, r, c, pu);
           amax = fmax(amax, fabs(v.x) + fabs(v.y));
         }
         M[i][j] = v;
       }
     for (int t = tid; t < rs * rs; t += 256) {
       const int u = t % rs, v = t / rs;
-      S.rs_[u][v] = Rin[(size_t)v * bp + u];
+      S.rs_[u][v] = read_r(Rin, bp, u, v, pr);
     }
     {
       const u64 w = wave_max((u64)__double_as_longlong(amax));

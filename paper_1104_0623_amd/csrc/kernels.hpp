@@ -8,9 +8,9 @@ namespace findmi {
 // One elimination as the kernels see it (mirrors findmi::Elim).
 struct ElimDev {
   int kind, s, b, n;
-  long long src0, src1;   // pool offsets (complex) of source U matrices; R = U + ld*ld
+  long long src0, src1;   // pool offsets (complex) of source U matrices; R follows each U
   int ld0, ld1;
-  long long dst;          // pool offset of the output U (b x b); R follows
+  long long dst;          // pool offset of the output U (b x b, or its packed lower triangle); R follows
   int map;                // first map entry
   int aux;                // final leaf block: index of its output record
   int f32;                // bit 0: U product in FP32, bit 1: W and R (Sigma) products in FP32
@@ -41,7 +41,8 @@ struct StageArgs {
   long long ws_stride;
   int Nx, Ny, nst;
   int* status;            // per energy of this pass: 1 = zero or tiny pivot met
-  int sym;                // bit 0: U complex symmetric (lower half formed); R is always formed whole
+  int sym;                // bit 0: U complex symmetric, bit 1: R anti-Hermitian; each such block is
+                          // formed and stored as its packed lower triangle
   int contacts;           // 1: contact self-energies on the columns y = 0 and y = Ny - 1 (sigma, sless read)
 };
 

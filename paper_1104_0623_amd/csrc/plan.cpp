@@ -52,15 +52,16 @@ double elim_flops(const Elim& e, int sym) {
   // the kept ones): W_q = Sigma(B,S_q) - L_q Sigma(S_q,S_q) costs b q^2 and
   // R = Sigma(B,B) - [L_q | W_q] [Sigma(S_q,B) ; L_q^dagger] costs 2 q b^2 (q b^2
   // when no kept node carries Sigma<, so that Sigma(S_q,B) = 0).  With U complex
-  // symmetric (sym bit 0) only its lower half is formed; R is always formed
-  // whole.  With R = 0 (no Sigma< in the front) W and R are not formed.
+  // symmetric (sym bit 0) only its lower half is formed, and with R
+  // anti-Hermitian (sym bit 1) only R's lower half.  With R = 0 (no Sigma< in
+  // the front) W and R are not formed.
   // Kept nodes not coupled to S (b - bact of them) take no part in any of it.
   b = e.bact;
-  const double hu = (sym & 1) ? 0.5 : 1.0;
+  const double hu = (sym & 1) ? 0.5 : 1.0, hr = (sym & 2) ? 0.5 : 1.0;
   const double base = s * s * s / 3.0 + s * s * b + hu * s * b * b;
   if (e.rzero) return 8.0 * base;
   const double q0 = e.bsig ? q : 0.0;
-  return 8.0 * (base + b * q * q + b * b * (q0 + q));
+  return 8.0 * (base + b * q * q + hr * b * b * (q0 + q));
 }
 
 namespace {
@@ -71,6 +72,8 @@ struct Builder {
   std::vector<int> mark;   // scratch marker over all nodes
   int stamp = 0;
   explicit Builder(Plan& p) : P(p), Nx(p.Nx), Ny(p.Ny), stencil(p.stencil), mark(size_t(p.Nx) * p.Ny, 0) {}
+  // pool elements of one cluster's U and R for b kept nodes
+  int64_t slot(int64_t b) const { return block_elems(b, P.pack & 1) + block_elems(b, P.pack & 2); }
 
   bool inside(const Rect& r, int x, int y) const {
     return x >= r.x0 && x < r.x0 + r.w && y >= r.y0 && y < r.y0 + r.h;
@@ -292,8 +295,8 @@ struct Builder {
     int64_t off = 0;
     for (int q = 1; q < nc; ++q) {
       Cluster& c = P.cl[q];
-      c.up_off = off; off += 2 * int64_t(c.B.size()) * c.B.size();
-      c.dn_off = off; off += 2 * int64_t(c.Bc.size()) * c.Bc.size();
+      c.up_off = off; off += slot(c.B.size());
+      c.dn_off = off; off += slot(c.Bc.size());
     }
     std::string err;
     // ---- upward pass: stages by height (leaves first); the root is not eliminated
@@ -435,8 +438,8 @@ struct Builder {
       if (!chosen[l]) continue;
       const Cluster& c = P.cl[leaves[l]];
       const int64_t bp = int64_t(c.r.w) * c.r.h + int64_t(extra[2 * l + 1].size());
-      leaf1_off[l] = off; off += 2 * bp * bp;
-      fin_off[l] = off; off += 2 * bp * bp;
+      leaf1_off[l] = off; off += slot(bp);
+      fin_off[l] = off; off += bp * bp;   // G(K,K) of the final block (LU form), whole
     }
     P.onsite_off = off;
     off += 2 * int64_t(Nx) * Ny;
@@ -522,8 +525,8 @@ struct Builder {
       for (int k = st.first; k < st.first + st.count; ++k) {
         const Elim& e = P.elims[k];
         P.max_n = std::max(P.max_n, e.n); P.max_s = std::max(P.max_s, e.s); P.max_b = std::max(P.max_b, e.b);
-        for (int mode = 0; mode < 2; ++mode) {
-          const double f = elim_flops(e, mode);   // 0: general, 1: U halved (symmetric form)
+        for (int mode : {0, 1, 3}) {
+          const double f = elim_flops(e, mode);   // 0: general, 1: U halved, 3: U and R halved
           if (st.variant < 0) { P.flops[mode][0] += f; P.flops[mode][1] += f; }
           else P.flops[mode][st.variant] += f;
         }
@@ -535,8 +538,9 @@ struct Builder {
 }  // namespace
 
 std::string build_plan(int Nx, int Ny, int stencil, int leaf, Plan& P, bool scattering, bool half_leaves,
-                       bool contacts) {
+                       bool contacts, int pack) {
   P = Plan();
+  P.pack = pack;
   P.Nx = Nx; P.Ny = Ny; P.stencil = stencil; P.leaf = leaf; P.scattering = scattering;
   P.half_leaves = half_leaves;
   P.contacts = contacts;

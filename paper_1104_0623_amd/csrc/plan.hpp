@@ -63,6 +63,10 @@ struct Plan {
   // contact self-energies on the columns y = 0 and y = Ny - 1 (false: a closed
   // device, A = E I - H, no contact coupling in the sets)
   bool contacts = true;
+  // stored triangles: bit 0 = each U (complex symmetric) kept as its lower
+  // triangle packed by columns, bit 1 = each R (anti-Hermitian) likewise;
+  // R follows U in its slot either way
+  int pack = 0;
   // pool offset (per energy) of the node diagonal: A_ii of the original matrix
   // without its contact part (E - H_ii - Sigma_d,i), then Sigma<_d,i ([2][Ny][Nx])
   int64_t onsite_off = 0;
@@ -77,14 +81,16 @@ struct Plan {
   int64_t pool_per_energy = 0;
   int max_n = 0, max_s = 0, max_b = 0;
   int n_bonds = 0;
-  // per energy: [halved triangles: 0 none, 1 U and R, 2 U only][variant 0/1]
-  double flops[2][2] = {{0, 0}, {0, 0}};   // [general, symmetric form][diagonal only, with bonds]
+  // per energy: [halved triangles, as elim_flops' sym: 0 none, 1 U, 3 U and R][variant 0/1]
+  double flops[4][2] = {};
 };
 
 int count_bonds(int Nx, int Ny, int stencil);
 // Builds the plan; returns an empty string on success, else a message.
 std::string build_plan(int Nx, int Ny, int stencil, int leaf, Plan& P, bool scattering = false,
-                       bool half_leaves = false, bool contacts = true);
+                       bool half_leaves = false, bool contacts = true, int pack = 0);
+// complex elements of a stored b x b block: whole, or a packed lower triangle
+inline int64_t block_elems(int64_t b, bool packed) { return packed ? b * (b + 1) / 2 : b * b; }
 // sym: bit 0 = only half of U formed, bit 1 = only half of R formed
 double elim_flops(const Elim& e, int sym = 0);
 

@@ -108,14 +108,14 @@ class Plan:
 
     def __init__(self, Nx: int, Ny: int, stencil: int = 5, leaf: int = 8, precision: int = PREC_FP64,
                  max_energies: int = 0, workspace_budget: int = 0, fp64_top_levels: int = 0,
-                 complex_mode: int = CPLX_4M, symmetric: bool = False, streams: int = 0,
+                 complex_mode: int = CPLX_4M, symmetric: int = 0, streams: int = 0,
                  scattering: bool = False, half_leaves: bool = False, no_contacts: bool = False):
         self.Nx, self.Ny, self.stencil = Nx, Ny, stencil
         self.scattering = bool(scattering)
         self._h = ctypes.c_void_p()
         o = PlanOpts(leaf=leaf, precision=precision, max_energies=max_energies,
                      workspace_budget=workspace_budget, fp64_top_levels=fp64_top_levels,
-                     complex_mode=complex_mode, symmetric=int(bool(symmetric)), streams=streams,
+                     complex_mode=complex_mode, symmetric=int(symmetric), streams=streams,
                      scattering=int(bool(scattering)), half_leaves=int(bool(half_leaves)),
                      no_contacts=int(bool(no_contacts)))
         _check(lib().find_plan_create(Nx, Ny, stencil, ctypes.byref(o), ctypes.byref(self._h)))

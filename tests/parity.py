@@ -10,6 +10,12 @@ import numpy as np
 
 TOL = 1e-10
 ENTRY_FLOOR = 1e-3
+# G< of the symmetric form that also halves R (symmetric = 2): R's lower
+# triangle mirrored to an exactly anti-Hermitian R changes the rounding that
+# G R G^dagger amplifies near resonances; a numpy execution of the same plan
+# with LAPACK solves gave 1.8e-8 on a 64 x 128 9-point mesh, the GPU path
+# 1.6e-8 there, 3e-8 at 128 x 128 (energy 128) and 7.9e-8 at 512 x 512.
+PACKED_R_TOL = 2e-7
 
 
 def nrel(x, ref):
@@ -29,11 +35,14 @@ def erel(x, ref, floor=ENTRY_FLOOR, norm=None):
     return float(np.max(np.abs(x[sel] - ref[sel]) / np.abs(ref[sel])))
 
 
-def compare(out, ref, prob, bonds=True, tol=TOL, etol=None, label="", energies=None, ref_index=None):
+def compare(out, ref, prob, bonds=True, tol=TOL, etol=None, label="", energies=None, ref_index=None,
+            gless_tol=None):
     """Every energy e of `energies` (default all) of `out` against entry
     ref_index[e] (default e) of `ref`: normwise <= tol and entrywise <= etol
     (default 100 tol) for diag G, diag G<, bond G and bond G<; bond J
-    normwise.  Returns the largest errors seen."""
+    normwise.  With gless_tol, the G< outputs (diag G<, bond G<, bond J)
+    are held to gless_tol (entrywise 100 gless_tol) instead.  Returns the
+    largest errors seen."""
     etol = 100 * tol if etol is None else etol
     nE = out["diag_G"].shape[0]
     energies = range(nE) if energies is None else energies
@@ -45,10 +54,12 @@ def compare(out, ref, prob, bonds=True, tol=TOL, etol=None, label="", energies=N
             n_err, e_err = nrel(out[k][e], ref[k][r]), erel(out[k][e], ref[k][r])
             worst["norm"] = max(worst["norm"], n_err)
             worst["entry"] = max(worst["entry"], e_err)
-            assert n_err <= tol, (label, e, k, "normwise", n_err)
-            assert e_err <= etol, (label, e, k, "entrywise", e_err)
+            t, et = (gless_tol, 100 * gless_tol) if gless_tol is not None and "Gless" in k else (tol, etol)
+            assert n_err <= t, (label, e, k, "normwise", n_err)
+            assert e_err <= et, (label, e, k, "entrywise", e_err)
         if bonds and ref["bond_G"].shape[1]:
             hmax = np.max(np.abs(prob["H"][1:]))
             scale = np.max(np.abs(ref["bond_J"][r])) + hmax * np.max(np.abs(ref["bond_Gless"][r]))
-            assert np.max(np.abs(out["bond_J"][e] - ref["bond_J"][r])) <= tol * scale, (label, e, "bond_J")
+            tj = tol if gless_tol is None else gless_tol
+            assert np.max(np.abs(out["bond_J"][e] - ref["bond_J"][r])) <= tj * scale, (label, e, "bond_J")
     return worst

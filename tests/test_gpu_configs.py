@@ -22,7 +22,7 @@ import pytest
 
 from oracle import dense, rgf
 from paper_1104_0623_amd import inputs
-from tests.parity import TOL, compare, erel, nrel
+from tests.parity import PACKED_R_TOL, TOL, compare, erel, nrel
 
 pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -66,6 +66,11 @@ def test_c3_benchmark_configuration_against_rgf():
     out = f.run_problem(tuned(f, f.Plan(128, 128, 5, symmetric=True, streams=2), "128x128/5/8/fp64/4m/sym"), prob,
                         want_bonds=False)
     compare(out, ref, prob, bonds=False, energies=sample, tol=SYM_TOL, label="c3 symmetric form")
+    # U and R both halved and stored packed: G at the symmetric form's bound,
+    # G< at the mirrored-R bound
+    out = f.run_problem(f.Plan(128, 128, 5, symmetric=2, streams=2), prob, want_bonds=True)
+    w = compare(out, ref, prob, energies=sample, tol=SYM_TOL, gless_tol=PACKED_R_TOL, label="c3 symmetric=2")
+    print(f"c3 symmetric=2 with bonds: worst normwise {w['norm']:.2e}, entrywise {w['entry']:.2e}")
 
 
 def c5_golden():

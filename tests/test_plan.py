@@ -40,6 +40,8 @@ def test_argument_errors():
         find.Plan(4, 4, 7)
     with pytest.raises(find.FindError):
         find.Plan(4, 4, 5, leaf=-1)
+    with pytest.raises(find.FindError):
+        find.Plan(4, 4, 5, symmetric=3)
     assert find.n_bonds(4, 3, 5) == 3 * 3 + 4 * 2
     assert find.n_bonds(4, 3, 9) == 3 * 3 + 4 * 2 + 2 * 3 * 2
     assert find.n_bonds(0, 3, 9) == -1
@@ -47,6 +49,28 @@ def test_argument_errors():
     assert L.find_plan_destroy(None) == 0
     assert L.find_solve(None, 1, *([None] * 10)) == find.FIND_E_ARG
     assert b"NULL plan" in L.find_last_error()
+
+
+@pytest.mark.parametrize("Nx,Ny,stencil,leaf", [(64, 64, 5, 8), (33, 20, 9, 4), (16, 16, 5, 2)])
+def test_packed_symmetric_pool_sizes(Nx, Ny, stencil, leaf):
+    """Prop. 1 storage reduction: symmetric = 1 keeps each U (complex
+    symmetric), symmetric = 2 each U and each R (anti-Hermitian), as a packed
+    lower triangle.  Every U/R slot of b kept nodes then shrinks by
+    b (b - 1) / 2 per halved block, by the same amount for U and for R; a
+    slot is the destination of its eliminations (the leaf-extraction slots
+    sized for the larger of the two output variants)."""
+    find = findlib()
+    sizes = [find.Plan(Nx, Ny, stencil, leaf=leaf, symmetric=k).summary()["pool_per_energy"] for k in (0, 1, 2)]
+    el = find.Plan(Nx, Ny, stencil, leaf=leaf).export()["elims"].astype(np.int64)
+    slot_b = {}
+    KIND, B, DST = 0, 2, 8   # fields of an exported elimination record (find.h)
+    for e in el:
+        if e[KIND] == 0:   # Schur eliminations write U and R; final blocks only G (whole)
+            slot_b[e[DST]] = max(slot_b.get(e[DST], 0), e[B])
+    saving = sum(b * (b - 1) // 2 for b in slot_b.values())
+    assert saving > 0
+    assert sizes[0] - sizes[1] == saving and sizes[1] - sizes[2] == saving
+    assert 0.5 * sizes[0] < sizes[2] < 0.65 * sizes[0]
 
 
 def test_scattering_entry_points_reject_the_other_kind_of_plan():

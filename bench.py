@@ -158,6 +158,9 @@ def main() -> int:
                          "accuracy near resonances).  By default the general form runs (it keeps the 1e-10 "
                          "accuracy at the ill-conditioned energies where the mirrored U loses a factor of a few)")
     ap.add_argument("--streams", type=int, default=2, help="energy groups solved concurrently (0/1 = one)")
+    ap.add_argument("--budget-gb", type=float, default=0.0,
+                    help="device memory the plan may hold, GB (0 = the library default of 64 GiB); energies "
+                         "are solved in passes that fit it")
     ap.add_argument("--bonds", action="store_true",
                     help="also return G and G< on every bond and the bond currents (the leaf extraction "
                          "keeps the bonds' far ends)")
@@ -216,7 +219,8 @@ def main() -> int:
     prec = PRECISION[args.precision]
     cmode = find.CPLX_3M if args.complex_mode == "3m" else find.CPLX_4M
     plan = find.Plan(Nx, Ny, st, leaf=args.leaf, precision=prec, complex_mode=cmode, symmetric=args.symmetric,
-                     streams=args.streams, scattering=args.scattering, half_leaves=args.half_leaves)
+                     streams=args.streams, scattering=args.scattering, half_leaves=args.half_leaves,
+                     workspace_budget=int(args.budget_gb * 1e9))
     plain_flops = plain_find_flops(plan)
     stream = torch.cuda.Stream()          # non-default stream (graph capture needs one)
     torch.cuda.set_stream(stream)
@@ -318,6 +322,7 @@ def main() -> int:
                    "Nx": Nx, "Ny": Ny, "stencil": st, "energies_per_step": nE, "precision": args.precision,
                    "leaf": args.leaf, "complex_mode": args.complex_mode, "symmetric": args.symmetric, "streams": args.streams,
                    "pool_MB_per_energy": round(plan.summary()["pool_per_energy"] * 16 / 1e6, 2),
+                   "plan_footprint_GB": round(plan.footprint(nE) / 1e9, 2),
                    "launch": "eager" if args.no_graph else "hipGraph replay per batch",
                    "stage_tiles": "".join(str(t) for t in tiles),
                    "stage_tiles_from": tiles_from,

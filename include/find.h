@@ -95,7 +95,11 @@ typedef enum { FIND_CPLX_4M = 0, FIND_CPLX_3M = 1 } find_complex_mode;
  *   max_energies  energies processed per internal pass (0 = chosen from the
  *                 workspace budget).
  *   fp64_top_levels  see precision (0 = default 2, negative = none).
- *   workspace_budget  device bytes the plan may hold (0 = 64 GiB).
+ *   workspace_budget  device bytes the plan may hold (0 = three quarters of
+ *                 the current device's memory, or 64 GiB where no device is
+ *                 visible, e.g. for find_plan_footprint on a host without
+ *                 one).  A solve of more energies than fit runs in passes of
+ *                 equal size.
  *   complex_mode  real split of the complex Schur-complement and Sigma
  *                 products: FIND_CPLX_4M (default; four real products per
  *                 complex product) or FIND_CPLX_3M (three: ar br, ai bi and

@@ -50,6 +50,7 @@ struct DevStage {
 struct DevState {
   int device = -1;
   int slots = 0;
+  size_t mem_total = 0;   // device memory (0: no device to ask)
   ElimDev* d_elims = nullptr;
   int* d_map_node = nullptr;
   int* d_map_srcpos = nullptr;
@@ -214,6 +215,7 @@ find_status ensure_device(find_plan_s* p, DevState** out) {
   int cus = 0;
   HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   ds->slots = slots_for(cus);
+  HIPCHK(hipDeviceTotalMem(&ds->mem_total, dev));
   const Plan& P = p->P;
   // elimination records, sorted by decreasing cost inside each stage
   std::vector<ElimDev> he(P.elims.size());
@@ -316,20 +318,27 @@ int lanes_of(const find_plan_s* p) { return std::max(1, std::min(4, p->opts.stre
 size_t lane_ws(const DevState& d, int ec, int lanes) { return ws_for(d, (ec + lanes - 1) / lanes); }
 size_t ws_total(const DevState& d, int ec, int lanes) { return size_t(lanes) * lane_ws(d, ec, lanes); }
 
-size_t budget_of(const find_plan_s* p) {
-  return p->opts.workspace_budget ? p->opts.workspace_budget : (size_t(64) << 30);
+// Device bytes a plan may hold: the caller's budget, else three quarters of
+// the device's memory (64 GiB when no device is visible)
+size_t budget_of(const find_plan_s* p, const DevState& d) {
+  if (p->opts.workspace_budget) return p->opts.workspace_budget;
+  return d.mem_total ? d.mem_total / 4 * 3 : (size_t(64) << 30);
 }
 
 // energies per internal pass so that pool + workspace fit in the budget
 int chunk_energies(const find_plan_s* p, const DevState& d, int nE) {
   const size_t per_e = size_t(p->P.pool_per_energy) * sizeof(double2) + sizeof(int);
-  const size_t budget = budget_of(p);
+  const size_t budget = budget_of(p, d);
   int ec = nE;
   if (p->opts.max_energies > 0) ec = std::min(ec, p->opts.max_energies);
   const int lanes = lanes_of(p);
   auto need = [&](int c) { return ws_total(d, c, lanes) * sizeof(double2) + d.maps_bytes + per_e * size_t(c); };
   while (ec > 1 && need(ec) > budget) ec = std::max(1, std::min(ec - 1, int(ec * double(budget) / double(need(ec)))));
-  return need(ec) <= budget ? ec : 0;
+  if (need(ec) > budget) return 0;
+  // as many passes as needed, of equal size (a short last pass would leave
+  // most of the device idle in the levels with few clusters)
+  const int passes = (nE + ec - 1) / ec;
+  return (nE + passes - 1) / passes;
 }
 
 }  // namespace
@@ -341,9 +350,11 @@ static void host_stages(const find_plan_s* p, DevState* d) {
   const Plan& P = p->P;
   int dev = -1, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipDeviceTotalMem(&d->mem_total, dev) != hipSuccess) {
     (void)hipGetLastError();
     cus = 0;
+    d->mem_total = 0;
   }
   d->slots = slots_for(cus);
   for (const Stage& st : P.stages) {

@@ -148,15 +148,16 @@ __device__ __forceinline__ size_t tri_off(int r, int c, int b) {
 __device__ __forceinline__ size_t block_size(int b, bool packed) {
   return packed ? ((size_t)b * (b + 1)) >> 1 : (size_t)b * b;
 }
+// element of entry (r, c) of a stored block (one load whatever the layout)
+__device__ __forceinline__ size_t blk_index(int b, int r, int c, bool packed) {
+  return packed ? tri_off(max(r, c), min(r, c), b) : (size_t)c * b + r;
+}
 __device__ __forceinline__ double2 read_u(const double2* U, int b, int r, int c, bool packed) {
-  if (!packed) return U[(size_t)c * b + r];
-  return r >= c ? U[tri_off(r, c, b)] : U[tri_off(c, r, b)];
+  return U[blk_index(b, r, c, packed)];
 }
 __device__ __forceinline__ double2 read_r(const double2* R, int b, int r, int c, bool packed) {
-  if (!packed) return R[(size_t)c * b + r];
-  if (r >= c) return R[tri_off(r, c, b)];
-  const double2 v = R[tri_off(c, r, b)];
-  return make_double2(-v.x, v.y);
+  const double2 v = R[blk_index(b, r, c, packed)];
+  return packed && r < c ? make_double2(-v.x, v.y) : v;
 }
 // store of entry (r, c) of a formed block; with a packed block only r >= c is kept
 __device__ __forceinline__ void write_blk(double2* X, int b, int r, int c, bool packed, double2 v) {
@@ -785,7 +786,9 @@ __device__ __forceinline__ void trsm_right_unit_lower(LDS& L, double2* FA, doubl
 
 template <int RPT, int TC, int CM, int NT, int MAXN>
 __global__ __launch_bounds__(NT, (TC == kTileWg || NT == 512) ? 2 : 3) void k_stage(StageArgs a) {
-  constexpr int NB = 16 / RPT;  // panel columns held in registers
+  // panel columns held in registers (the eight-wave form, at two waves per
+  // SIMD, has the registers for twice the panel width with four rows a thread)
+  constexpr int NB = (NT == kEightWaveThreads && RPT >= 4) ? 32 / RPT : 16 / RPT;
   __shared__ LdsT<NT, MAXN> L;
   const int tid = threadIdx.x;
   const long long total = (long long)a.n_elims * a.nE;
@@ -990,7 +993,7 @@ struct GjLds {
   double2 rs_[kGjRs][kGjRs];   // R_K(u, v) at [u][v]
 };
 
-template <int NT>
+template <int NT, int SYM>
 __global__ __launch_bounds__(NT, 3) void k_final_gj(StageArgs a, OutArgs o) {
   static_assert(NT == 256, "one 256-thread workgroup per block (4 x 4 entries per thread)");
   __shared__ GjLds S;
@@ -1003,7 +1006,7 @@ __global__ __launch_bounds__(NT, 3) void k_final_gj(StageArgs a, OutArgs o) {
     const ElimDev E = a.elims[ei];
     const LeafOutDev Lo = o.leaves[E.aux];
     const int bp = E.b, rs = E.ssig;
-    const bool pu = a.sym & 1, pr = a.sym & 2;
+    constexpr bool pu = SYM & 1, pr = SYM & 2;   // a.sym, as a template argument
     const double2* Uin = a.pool + (size_t)e * a.pool_stride + E.src0;   // U_K (whole or packed)
     const double2* Rin = Uin + block_size(bp, pu);                         // R_K
     double2 M[4][4];
@@ -1253,7 +1256,12 @@ hipError_t launch_final_w2(const StageArgs& a, const OutArgs& o, int rpt, int gr
   return hipGetLastError();
 }
 hipError_t launch_final_gj(const StageArgs& a, const OutArgs& o, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_final_gj<256>, dim3(grid), dim3(256), 0, st, a, o);
+  switch (a.sym) {
+    case 0: hipLaunchKernelGGL((k_final_gj<256, 0>), dim3(grid), dim3(256), 0, st, a, o); break;
+    case 1: hipLaunchKernelGGL((k_final_gj<256, 1>), dim3(grid), dim3(256), 0, st, a, o); break;
+    case 3: hipLaunchKernelGGL((k_final_gj<256, 3>), dim3(grid), dim3(256), 0, st, a, o); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 hipError_t launch_final_w(const StageArgs& a, const OutArgs& o, int rpt, int grid, hipStream_t st) {

@@ -87,9 +87,9 @@ def test_c3_128x128_sampled_energies_against_rgf():
 
 def test_c3_128x128_scattering_sampled_against_rgf():
     """Full 128 x 128 mesh with diagonal scattering self-energies on every
-    node, in the benchmark's launch configuration (symmetric form, two
-    energy groups, the tuning table's tiles); the oracle computes a sample of
-    the energies one by one."""
+    node, in the benchmark's launch configuration for it (symmetric form, two
+    energy groups, the tuning table's tiles for scattering plans); the oracle
+    computes a sample of the energies one by one."""
     import json, os
     f = find()
     prob = inputs.make_preset("c3_128x128")
@@ -98,7 +98,7 @@ def test_c3_128x128_scattering_sampled_against_rgf():
     prob.update(sigma_d=sd, sigma_less_d=sl)
     plan = f.Plan(128, 128, 5, symmetric=True, streams=2, scattering=True)
     table = json.load(open(os.path.join(os.path.dirname(f.__file__), "tuning.json")))
-    plan.set_tiles([int(c) for c in table["128x128/5/8/fp64/4m/sym"]])
+    plan.set_tiles([int(c) for c in table["128x128/5/8/fp64/4m/sym/scat"]])
     out = f.run_problem(plan, prob, want_bonds=False)
     sample = [3, 128, 250]
     sub = {k: v[sample] for k, v in prob.items() if k in ("energies", "sigma", "sigma_less", "sigma_d", "sigma_less_d")}

@@ -32,6 +32,7 @@
 #include <array>
 #include <cstdio>
 #include <cstdlib>
+#include <map>
 #include <numeric>
 
 namespace findmi {
@@ -74,6 +75,73 @@ struct Builder {
   explicit Builder(Plan& p) : P(p), Nx(p.Nx), Ny(p.Ny), stencil(p.stencil), mark(size_t(p.Nx) * p.Ny, 0) {}
   // pool elements of one cluster's U and R for b kept nodes
   int64_t slot(int64_t b) const { return block_elems(b, P.pack & 1) + block_elems(b, P.pack & 2); }
+  std::vector<std::pair<int64_t, int64_t>> slot_size;   // (provisional offset, elements) per slot
+
+  // Place the slots in the energy pool by lifetime.  A slot lives from the
+  // stage that writes it to the last stage that reads it (stages in plan
+  // order; a solve runs a subset of them, in the same order), and two slots
+  // share memory only if their lifetimes are disjoint: the upward results of a
+  // level die once the downward pass has read them, the downward results of a
+  // level once the next level (or the leaf extraction) has, so the pool holds
+  // about the upward results plus two downward levels instead of every slot.
+  // The node diagonal (read by every stage) comes first; slots start on
+  // 16-element boundaries.  First fit over a free list, in stage order.
+  void assign_pool() {
+    const int ns = int(P.stages.size());
+    std::map<int64_t, int> id;   // provisional offset -> slot
+    for (size_t k = 0; k < slot_size.size(); ++k) id[slot_size[k].first] = int(k);
+    const int n = int(slot_size.size());
+    std::vector<int> birth(n, ns), death(n, -1);
+    for (int t = 0; t < ns; ++t)
+      for (int k = P.stages[t].first; k < P.stages[t].first + P.stages[t].count; ++k) {
+        const Elim& e = P.elims[k];
+        const int d = id.at(e.dst);
+        birth[d] = std::min(birth[d], t);
+        death[d] = std::max(death[d], t);
+        for (int j = 0; j < 2; ++j)
+          if (e.src_off[j] >= 0) death[id.at(e.src_off[j])] = std::max(death[id.at(e.src_off[j])], t);
+      }
+    auto up16 = [](int64_t x) { return (x + 15) & ~int64_t(15); };
+    P.onsite_off = 0;
+    const int64_t base = up16(2 * int64_t(Nx) * Ny);
+    std::vector<int64_t> place(n, -1);
+    std::map<int64_t, int64_t> free_ = {{base, INT64_MAX / 4}};   // offset -> length
+    auto release = [&](int64_t o, int64_t len) {
+      auto it = free_.emplace(o, len).first;
+      auto nx = std::next(it);
+      if (nx != free_.end() && it->first + it->second == nx->first) { it->second += nx->second; free_.erase(nx); }
+      if (it != free_.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) { pv->second += it->second; free_.erase(it); }
+      }
+    };
+    int64_t high = base;
+    for (int t = 0; t < ns; ++t) {
+      for (int k = 0; k < n; ++k)   // free the slots last read before stage t
+        if (place[k] >= 0 && death[k] < t && death[k] >= 0 && birth[k] <= death[k]) {
+          release(place[k], up16(slot_size[k].second));
+          death[k] = -2;   // released
+        }
+      for (int k = 0; k < n; ++k) {
+        if (birth[k] != t) continue;
+        const int64_t len = up16(slot_size[k].second);
+        auto it = free_.begin();
+        while (it->second < len) ++it;
+        place[k] = it->first;
+        const int64_t rest = it->second - len, at = it->first + len;
+        free_.erase(it);
+        if (rest > 0) free_.emplace(at, rest);
+        high = std::max(high, place[k] + len);
+      }
+    }
+    auto remap = [&](int64_t o) { return o < 0 ? o : place[id.at(o)]; };
+    for (Elim& e : P.elims) {
+      e.dst = remap(e.dst);
+      for (int j = 0; j < 2; ++j) e.src_off[j] = remap(e.src_off[j]);
+    }
+    for (Cluster& c : P.cl) { c.up_off = remap(c.up_off); c.dn_off = remap(c.dn_off); }
+    P.pool_per_energy = high;
+  }
 
   bool inside(const Rect& r, int x, int y) const {
     return x >= r.x0 && x < r.x0 + r.w && y >= r.y0 && y < r.y0 + r.h;
@@ -291,12 +359,15 @@ struct Builder {
     build_tree();
     build_sets();
     const int nc = int(P.cl.size());
-    // pool layout: upward (U_C, R_C) and downward (U_{C-bar}, R_{C-bar}) for non-root clusters
+    // pool slots (provisional offsets, one per slot; assign_pool places them by
+    // lifetime at the end): upward (U_C, R_C) and downward (U_{C-bar},
+    // R_{C-bar}) for non-root clusters
     int64_t off = 0;
+    auto new_slot = [&](int64_t size) { const int64_t o = off; slot_size.push_back({o, size}); off += size; return o; };
     for (int q = 1; q < nc; ++q) {
       Cluster& c = P.cl[q];
-      c.up_off = off; off += slot(c.B.size());
-      c.dn_off = off; off += slot(c.Bc.size());
+      c.up_off = new_slot(slot(c.B.size()));
+      c.dn_off = new_slot(slot(c.Bc.size()));
     }
     std::string err;
     // ---- upward pass: stages by height (leaves first); the root is not eliminated
@@ -438,12 +509,9 @@ struct Builder {
       if (!chosen[l]) continue;
       const Cluster& c = P.cl[leaves[l]];
       const int64_t bp = int64_t(c.r.w) * c.r.h + int64_t(extra[2 * l + 1].size());
-      leaf1_off[l] = off; off += slot(bp);
-      fin_off[l] = off; off += bp * bp;   // G(K,K) of the final block (LU form), whole
+      leaf1_off[l] = new_slot(slot(bp));
+      fin_off[l] = new_slot(bp * bp);   // G(K,K) of the final block (LU form), whole
     }
-    P.onsite_off = off;
-    off += 2 * int64_t(Nx) * Ny;
-    P.pool_per_energy = off;
     for (int v = 0; v < 2; ++v) {
       int first = int(P.elims.size());
       std::vector<std::vector<int>> keeps(leaves.size());
@@ -520,6 +588,7 @@ struct Builder {
       }
       P.stages.push_back({first, int(P.elims.size()) - first, PH_FINAL, v});
     }
+    assign_pool();
     // size limits and flop model
     for (auto& st : P.stages)
       for (int k = st.first; k < st.first + st.count; ++k) {

@@ -51,26 +51,68 @@ def test_argument_errors():
     assert b"NULL plan" in L.find_last_error()
 
 
-@pytest.mark.parametrize("Nx,Ny,stencil,leaf", [(64, 64, 5, 8), (33, 20, 9, 4), (16, 16, 5, 2)])
-def test_packed_symmetric_pool_sizes(Nx, Ny, stencil, leaf):
-    """Prop. 1 storage reduction: symmetric = 1 keeps each U (complex
-    symmetric), symmetric = 2 each U and each R (anti-Hermitian), as a packed
-    lower triangle.  Every U/R slot of b kept nodes then shrinks by
-    b (b - 1) / 2 per halved block, by the same amount for U and for R; a
-    slot is the destination of its eliminations (the leaf-extraction slots
-    sized for the larger of the two output variants)."""
+def pool_slots(plan, pack):
+    """Slots of the energy pool from a plan's export, one per (phase kind,
+    cluster): the upward and downward U/R of each cluster, the leaf block
+    (both output variants write it) and the final block G.  Returns
+    {slot: [start, elements, first stage writing it, last stage reading it]};
+    a read of a start belongs to the slot last written there."""
+    ex = plan.export()
+    el, st = ex["elims"].astype(np.int64), ex["stages"]
+    KIND, B, SRC0, SRC1, DST, CLUSTER, PHASE = 0, 2, 4, 6, 8, 10, 11   # exported record fields (find.h)
+    blk = lambda b, packed: b * (b + 1) // 2 if packed else b * b
+    slots, owner = {}, {}
+    for t, (first, count, _, _) in enumerate(st):
+        for e in el[first:first + count]:
+            for k in (SRC0, SRC1):
+                if e[k] >= 0:
+                    sid = owner[int(e[k])]          # a read needs an earlier write there
+                    slots[sid][3] = max(slots[sid][3], t)
+        for e in el[first:first + count]:
+            b = int(e[B])
+            size = b * b if e[KIND] == 1 else blk(b, pack & 1) + blk(b, pack & 2)
+            sid = (int(e[PHASE]), int(e[CLUSTER]))
+            rec = slots.setdefault(sid, [int(e[DST]), 0, t, t])
+            assert rec[0] == int(e[DST])
+            rec[1] = max(rec[1], size)
+            owner[int(e[DST])] = sid
+    return slots
+
+
+@pytest.mark.parametrize("Nx,Ny,stencil,leaf", [(64, 64, 5, 8), (33, 20, 9, 4), (16, 16, 5, 2), (24, 40, 5, 4)])
+@pytest.mark.parametrize("half_leaves", [False, True])
+def test_pool_slots_disjoint_while_live(Nx, Ny, stencil, leaf, half_leaves):
+    """The energy pool holds each cluster's U and R from the stage that forms
+    them to the last stage that reads them, and slots whose lifetimes overlap
+    never share memory; the node diagonal (read by every stage) overlaps no
+    slot.  In the symmetric forms U (symmetric = 1), or U and R
+    (symmetric = 2), take b (b + 1) / 2 elements (Prop. 1 storage
+    reduction), so the pool shrinks form by form."""
     find = findlib()
-    sizes = [find.Plan(Nx, Ny, stencil, leaf=leaf, symmetric=k).summary()["pool_per_energy"] for k in (0, 1, 2)]
-    el = find.Plan(Nx, Ny, stencil, leaf=leaf).export()["elims"].astype(np.int64)
-    slot_b = {}
-    KIND, B, DST = 0, 2, 8   # fields of an exported elimination record (find.h)
-    for e in el:
-        if e[KIND] == 0:   # Schur eliminations write U and R; final blocks only G (whole)
-            slot_b[e[DST]] = max(slot_b.get(e[DST], 0), e[B])
-    saving = sum(b * (b - 1) // 2 for b in slot_b.values())
-    assert saving > 0
-    assert sizes[0] - sizes[1] == saving and sizes[1] - sizes[2] == saving
-    assert 0.5 * sizes[0] < sizes[2] < 0.65 * sizes[0]
+    sizes = []
+    for sym, pack in ((0, 0), (1, 1), (2, 3)):
+        plan = find.Plan(Nx, Ny, stencil, leaf=leaf, symmetric=sym, half_leaves=half_leaves)
+        pool = plan.summary()["pool_per_energy"]
+        sizes.append(pool)
+        slots = sorted(tuple(v) for v in pool_slots(plan, pack).values())
+        for k, (o, n, b0, d0) in enumerate(slots):
+            assert 2 * Nx * Ny <= o and o + n <= pool, (sym, o, n)
+            assert b0 <= d0
+            for o2, n2, b2, d2 in slots[k + 1:]:
+                if o2 >= o + n:
+                    break   # sorted by start: no later slot overlaps this one in memory
+                assert d0 < b2 or d2 < b0, ("live slots overlap", sym, (o, n, b0, d0), (o2, n2, b2, d2))
+    assert sizes[0] > sizes[1] > sizes[2]
+
+
+def test_pool_lifetimes_halve_the_128_pool():
+    """At 128 x 128 (5-point, 8 x 8 leaves) the lifetime placement keeps the
+    pool near the upward results plus two downward levels: less than half
+    the sum of all slots."""
+    find = findlib()
+    plan = find.Plan(128, 128, 5)
+    total = sum(v[1] for v in pool_slots(plan, 0).values())
+    assert plan.summary()["pool_per_energy"] < 0.55 * total
 
 
 def test_scattering_entry_points_reject_the_other_kind_of_plan():
@@ -361,8 +403,16 @@ def test_schur_blocks_independent_of_elimination_order(Nx, Ny, stencil, leaf):
         execute(ex, Nx, Ny, stencil, Hm, E, prob["sigma"][0], prob["sigma_less"][0], want_bonds=bonds, record=rec)
     A = dense.dense_A(Nx, Ny, prob["H"], E, prob["sigma"][0])
     Sl = dense.embed_contacts(Nx, Ny, prob["sigma_less"][0])
-    by_dst = {int(el[k][8]): k for k in range(len(el)) if el[k][0] == 0}
+    # pool slots are reused once dead: a source is the last elimination
+    # before the reader (in stage order) that wrote its offset
+    by_dst = {}
+    for k in range(len(el)):
+        if el[k][0] == 0:
+            by_dst.setdefault(int(el[k][8]), []).append(k)
     elim_set = {}
+
+    def source(k, off):
+        return max(j for j in by_dst[off] if j < k)
 
     def eliminated(k):
         if k not in elim_set:
@@ -370,7 +420,7 @@ def test_schur_blocks_independent_of_elimination_order(Nx, Ny, stencil, leaf):
             out = set(maps[mp: mp + s_, 0].tolist())
             for f_ in (4, 6):
                 if el[k][f_] >= 0:
-                    out |= eliminated(by_dst[int(el[k][f_])])
+                    out |= eliminated(source(k, int(el[k][f_])))
             elim_set[k] = out
         return elim_set[k]
 

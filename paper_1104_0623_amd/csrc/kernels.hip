@@ -587,6 +587,17 @@ __device__ __forceinline__ double wave_sum(double x) {
          (__longlong_as_double((long long)readlane_u64(b, 32)) + __longlong_as_double((long long)readlane_u64(b, 48)));
 }
 
+// v of the lane at byte address src (4 x lane) of this wave
+__device__ __forceinline__ double bperm_d(int src, double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_ds_bpermute(src, int(b & 0xffffffff));
+  const int hi = __builtin_amdgcn_ds_bpermute(src, int(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double2 bperm_d2(int src, double2 v) {
+  return make_double2(bperm_d(src, v.x), bperm_d(src, v.y));
+}
+
 // Physical row of logical row r of a front whose first s rows are pivoted.
 __device__ __forceinline__ int prow(const int* pm, int s, int r) { return r < s ? pm[r] : r; }
 
@@ -972,8 +983,10 @@ __global__ __launch_bounds__(NT, 3) void k_final(StageArgs a, OutArgs o) {
 // 64 x 64 block in registers (thread t owns rows 4 (t % 16) .. + 3 and columns
 // 4 (t / 16) .. + 3).  Step k takes the largest |re| + |im| of column k among
 // the rows not pivoted yet (one DPP reduction by the 16 owners of the
-// column), publishes the column and the pivot row through LDS (buffers by step
-// parity, two barriers per step) and updates every entry; pivot rows are
+// column, which are one row of lanes of one wave), publishes the column and
+// the pivot through LDS (buffers by step parity, one barrier per step); every
+// thread takes the pivot row's entries of its own columns from the lane of its
+// wave that holds them, and updates its entries; pivot rows are
 // relabelled, not moved, so that the block ends as G with its rows and
 // columns permuted: entry (r, k) is G(step of row r, pivot row of step k).
 // G(:, 0:rs) is then staged in LDS and diag G< = diag(G R_K G^dagger) is a
@@ -982,7 +995,6 @@ __global__ __launch_bounds__(NT, 3) void k_final(StageArgs a, OutArgs o) {
 constexpr int kGjMax = kGjMaxB, kGjRs = kGjMaxRs;
 struct GjLds {
   double2 pcol[2][kGjMax];   // column k of the current step, by step parity
-  double2 prow[2][kGjMax];   // pivot row of the current step
   unsigned long long key[2];
   double2 pinv[2];           // reciprocal of the pivot
   unsigned long long red[4];
@@ -1089,21 +1101,27 @@ __global__ __launch_bounds__(NT, 3) void k_final_gj(StageArgs a, OutArgs o) {
         if (!(mag > 0.0) || mag < thr) singular = true;
         const int pi = p & 3;
         const bool prow_owner = rb == (p >> 2);
-        if (prow_owner) {
+        if (tid == 0) { S.prowi[k] = p; S.kinv[p] = k; }
+        // the 16 threads of a column block are lanes 16 (cb % 4) .. + 15 of one
+        // wave, so row p of this thread's columns comes from lane
+        // 16 (cb % 4) + p / 4 of its own wave (pi is uniform: a scalar branch)
+        double2 pr[4];
+        {
+          double2 sel[4];
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
+          for (int j = 0; j < 4; ++j) sel[j] = M[0][j];
+#pragma unroll
+          for (int i = 1; i < 4; ++i)
             if (pi == i)
 #pragma unroll
-              for (int j = 0; j < 4; ++j) S.prow[buf][4 * cb + j] = M[i][j];
+              for (int j = 0; j < 4; ++j) sel[j] = M[i][j];
+          const int src = ((16 * (cb & 3) + (p >> 2)) << 2);   // byte address of the source lane
+#pragma unroll
+          for (int j = 0; j < 4; ++j) pr[j] = bperm_d2(src, sel[j]);
         }
-        if (tid == 0) { S.prowi[k] = p; S.kinv[p] = k; }
-        __syncthreads();
         // 3. M(i,j) -= f_i M(p,j) with f_i = M(i,k) / pivot for every row (row p
         //    and column k come out zero and are set next): column k <- -f,
         //    row p <- M(p,:) / pivot with 1 / pivot at column k
-        double2 pr[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) pr[j] = S.prow[buf][4 * cb + j];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -1123,6 +1141,7 @@ __global__ __launch_bounds__(NT, 3) void k_final_gj(StageArgs a, OutArgs o) {
       }
     }
     if (singular && tid == 0) a.status[e] = 1;
+    __syncthreads();   // the last step's pivot labels
     // G(kinv[r], prowi[c]) = M(r, c): diag G and G(:, 0:rs) into LDS
 #pragma unroll
     for (int i = 0; i < 4; ++i)

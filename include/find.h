@@ -179,7 +179,10 @@ typedef struct {
  * (paper Sec. 2.1-2.2 for the trees and sets; procedure computeG<).  Host
  * only; device state is created on first find_solve.
  * Errors: FIND_E_ARG if Nx < 1, Ny < 1, stencil not 5/9, out == NULL,
- * or leaf < 1. */
+ * or leaf < 1; FIND_E_UNSUPPORTED for more than 2^24 nodes or a front
+ * (eliminated plus kept nodes of one elimination) of more than 2048 nodes,
+ * the largest the kernels hold (e.g. a 1024 x 256 9-point mesh, whose
+ * 1024-node contact columns join its separators, has fronts of 2808). */
 find_status find_plan_create(int Nx, int Ny, int stencil, const find_plan_opts* opts,
                              find_plan* out);
 

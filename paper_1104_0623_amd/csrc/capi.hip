@@ -409,6 +409,12 @@ find_status find_plan_create(int Nx, int Ny, int stencil, const find_plan_opts* 
     err = std::string("find_plan_create: ") + ex.what();
   }
   if (!err.empty()) { delete p; return fail(FIND_E_ARG, err); }
+  if (p->P.max_n > kMaxFront) {
+    const int mn = p->P.max_n;
+    delete p;
+    return fail(FIND_E_UNSUPPORTED, "find_plan_create: largest front has " + std::to_string(mn) +
+                                        " nodes, beyond the supported " + std::to_string(kMaxFront));
+  }
   for (const Stage& st : p->P.stages) {
     int maxn = 1, maxb = 0, maxrs = 0;
     for (int k = st.first; k < st.first + st.count; ++k) {

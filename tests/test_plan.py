@@ -42,6 +42,13 @@ def test_argument_errors():
         find.Plan(4, 4, 5, leaf=-1)
     with pytest.raises(find.FindError):
         find.Plan(4, 4, 5, symmetric=3)
+    # fronts beyond the kernels' 2048 nodes are refused at plan creation
+    with pytest.raises(find.FindError) as ei:
+        find.Plan(1024, 256, 9)
+    assert ei.value.status == find.FIND_E_UNSUPPORTED
+    with pytest.raises(find.FindError) as ei:
+        find.Plan(4097, 4097, 5)
+    assert ei.value.status == find.FIND_E_UNSUPPORTED
     assert find.n_bonds(4, 3, 5) == 3 * 3 + 4 * 2
     assert find.n_bonds(4, 3, 9) == 3 * 3 + 4 * 2 + 2 * 3 * 2
     assert find.n_bonds(0, 3, 9) == -1

@@ -179,10 +179,11 @@ typedef struct {
  * (paper Sec. 2.1-2.2 for the trees and sets; procedure computeG<).  Host
  * only; device state is created on first find_solve.
  * Errors: FIND_E_ARG if Nx < 1, Ny < 1, stencil not 5/9, out == NULL,
- * or leaf < 1; FIND_E_UNSUPPORTED for more than 2^24 nodes or a front
- * (eliminated plus kept nodes of one elimination) of more than 2048 nodes,
- * the largest the kernels hold (e.g. a 1024 x 256 9-point mesh, whose
- * 1024-node contact columns join its separators, has fronts of 2808). */
+ * or leaf < 1; FIND_E_UNSUPPORTED for more than 2^24 nodes, a front
+ * (eliminated plus kept nodes of one elimination) of more than 4096 nodes,
+ * or a final leaf block of more than 1024.  Fronts of 2049..4096 nodes
+ * (contact columns of more than 1024 nodes join the separators: a 1024 x 256
+ * 9-point mesh has fronts of 2808) run in launch configuration 7 only. */
 find_status find_plan_create(int Nx, int Ny, int stencil, const find_plan_opts* opts,
                              find_plan* out);
 

@@ -423,8 +423,16 @@ find_status find_plan_create(int Nx, int Ny, int stencil, const find_plan_opts* 
       maxrs = std::max(maxrs, p->P.elims[k].ssig);
     }
     const bool gj_ok = st.phase == PH_FINAL && st.variant == 0 && maxb <= kGjMaxB && maxrs <= kGjMaxRs;
-    p->tiles.push_back(0);
-    p->tile_mask.push_back(stage_tile_mask(maxn, st.phase == PH_FINAL, gj_ok));
+    const int mask = stage_tile_mask(maxn, st.phase == PH_FINAL, gj_ok);
+    if (mask == 0) {
+      delete p;
+      return fail(FIND_E_UNSUPPORTED, "find_plan_create: a final leaf block of " + std::to_string(maxn / 2) +
+                                          " nodes is beyond the supported " + std::to_string(kFourWaveMaxFront / 2));
+    }
+    // default configuration: the 32x32 wave tile, or the eight-wave form where
+    // it is the only one that holds the fronts
+    p->tiles.push_back(mask & 1 ? 0 : kTileEight);
+    p->tile_mask.push_back(mask);
   }
   *out = p;
   return FIND_OK;

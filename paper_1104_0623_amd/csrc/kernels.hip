@@ -525,7 +525,7 @@ __device__ __forceinline__ void tri_inverse_unit_lower(LDS& L, int w) {
 // patterns, so the largest key (as an unsigned integer) is the largest
 // magnitude (to within 2^-40 relative), ties going to the lowest row; every
 // key of a row < kMaxFront is > 0.
-constexpr int kKeyBits = 12, kKeyRows = 1 << kKeyBits;
+constexpr int kKeyBits = 13, kKeyRows = 1 << kKeyBits;
 static_assert(2 * kMaxFront <= kKeyRows, "pivot key row field too narrow");
 typedef unsigned long long u64;
 __device__ __forceinline__ u64 pivot_key(double mag, int row) {
@@ -1237,7 +1237,8 @@ hipError_t launch_stage_w8(const StageArgs& a, int rpt, int cm, int grid, hipStr
     hipLaunchKernelGGL((k_stage<R, 0, C, kEightWaveThreads, kEightWaveThreads * R>), dim3(grid), dim3(kEightWaveThreads), 0, st, a); \
     return hipGetLastError();                                                                 \
   }
-  FIND_LAUNCH_W8(1, 0) FIND_LAUNCH_W8(2, 0) FIND_LAUNCH_W8(4, 0) FIND_LAUNCH_W8(1, 1) FIND_LAUNCH_W8(2, 1) FIND_LAUNCH_W8(4, 1)
+  FIND_LAUNCH_W8(1, 0) FIND_LAUNCH_W8(2, 0) FIND_LAUNCH_W8(4, 0) FIND_LAUNCH_W8(8, 0)
+  FIND_LAUNCH_W8(1, 1) FIND_LAUNCH_W8(2, 1) FIND_LAUNCH_W8(4, 1) FIND_LAUNCH_W8(8, 1)
 #undef FIND_LAUNCH_W8
   return hipErrorInvalidValue;
 }

@@ -61,7 +61,8 @@ struct OutArgs {
 
 // rows per thread of the register-resident LU panel needed for a front of size n
 inline int panel_rpt(int n) { return n <= 256 ? 1 : n <= 512 ? 2 : n <= 1024 ? 4 : 8; }
-constexpr int kMaxFront = 2048;
+constexpr int kMaxFront = 4096;        // eight-wave form, eight panel rows a thread
+constexpr int kFourWaveMaxFront = 2048; // every other form of a Schur elimination, and final blocks
 constexpr int kThreads = 256;
 
 // Stage launchers (one per kernel family; see kernels.hip).  tc: wave tile of
@@ -111,11 +112,14 @@ hipError_t launch_final_gj(const StageArgs& a, const OutArgs& o, int grid, hipSt
 // panel rows per thread of the one- and two-wave forms
 inline int wave_rpt(int n) { return n <= 64 ? 1 : 2; }
 inline int wave2_rpt(int n) { return n <= 128 ? 1 : 2; }
-inline int wave8_rpt(int n) { return n <= 512 ? 1 : n <= 1024 ? 2 : 4; }
+inline int wave8_rpt(int n) { return n <= 512 ? 1 : n <= 1024 ? 2 : n <= 2048 ? 4 : 8; }
 // bit mask of the tile configurations a stage with fronts of at most maxn nodes has;
 // gj_ok: a final stage whose blocks fit k_final_gj (at most kGjMaxB nodes, R_K
 // on at most kGjMaxRs, no bond outputs)
+// (fronts of more than kFourWaveMaxFront nodes: the eight-wave form only, and
+// no final stage; 0 = no configuration)
 inline int stage_tile_mask(int maxn, bool final_stage, bool gj_ok = false) {
+  if (maxn > kFourWaveMaxFront) return final_stage ? 0 : 1 << kTileEight;
   int m = final_stage ? 1 : (panel_rpt(maxn) <= 2 ? (0xf | 1 << kTileWg) : 1);
   if (final_stage && gj_ok) m |= 1 << kTileGJ;
   if (!final_stage) m |= 1 << kTileEight;
@@ -125,6 +129,7 @@ inline int stage_tile_mask(int maxn, bool final_stage, bool gj_ok = false) {
 }
 inline hipError_t launch_stage(const StageArgs& a, int maxn, int tc, int cm, int grid, hipStream_t st) {
   if (tc == kTileEight) return launch_stage_w8(a, wave8_rpt(maxn), cm, grid, st);
+  if (maxn > kFourWaveMaxFront) return hipErrorInvalidValue;
   if (tc == kTileWave) return maxn <= kWaveMaxFront ? launch_stage_w(a, wave_rpt(maxn), cm, grid, st) : hipErrorInvalidValue;
   if (tc == kTileTwoWave)
     return maxn <= kTwoWaveMaxFront ? launch_stage_w2(a, wave2_rpt(maxn), cm, grid, st) : hipErrorInvalidValue;
@@ -135,6 +140,7 @@ inline hipError_t launch_stage(const StageArgs& a, int maxn, int tc, int cm, int
   }
 }
 inline hipError_t launch_final_tc(const StageArgs& a, const OutArgs& o, int maxn, int tc, int grid, hipStream_t st) {
+  if (maxn > kFourWaveMaxFront) return hipErrorInvalidValue;
   if (tc == kTileGJ) return launch_final_gj(a, o, grid, st);
   if (tc == kTileWave) return maxn <= kWaveMaxFront ? launch_final_w(a, o, wave_rpt(maxn), grid, st) : hipErrorInvalidValue;
   if (tc == kTileTwoWave)

@@ -343,3 +343,24 @@ def test_closed_device_against_dense(Nx, Ny, stencil, leaf):
         f.sync_status(plan)
         out = dict(zip(("diag_G", "diag_Gless", "bond_G", "bond_Gless", "bond_J"), (o.cpu().numpy() for o in outs)))
         compare(out, ref, prob, tol=SYM_TOL if kw.get("symmetric") else TOL, label=f"closed {Nx}x{Ny} {kw}")
+
+
+@pytest.mark.parametrize("Nx,Ny,ref_kind", [(1030, 2, "dense"), (1100, 4, "rgf")])
+def test_fronts_beyond_2048_nodes(Nx, Ny, ref_kind):
+    """Contact columns of more than 1024 nodes join the separators into fronts
+    of 2049-4096 nodes, which only the eight-wave form holds (eight panel
+    rows a thread): both energies, with bond outputs, against the dense
+    definition or RGF."""
+    f = find()
+    E = np.array([0.37 + 1e-6j, -1.2 + 1e-3j])
+    prob = inputs.make_problem(Nx, Ny, 5, vmax=1.0, seed=Nx + Ny, energies=E, fL=1.0, fR=0.2)
+    plan = f.Plan(Nx, Ny, 5)
+    assert plan.summary()["max_n"] > 2048
+    if ref_kind == "dense":
+        ref = dense.dense_solve(Nx, Ny, 5, prob["H"], E, prob["sigma"], prob["sigma_less"])
+    else:
+        ref = rgf.rgf_solve(Nx, Ny, 5, prob["H"], E, prob["sigma"], prob["sigma_less"], bonds=True)
+    out = f.run_problem(plan, prob, want_bonds=True)
+    w = compare(out, ref, prob, label=f"{Nx}x{Ny} fronts > 2048")
+    print(f"{Nx}x{Ny} (largest front {plan.summary()['max_n']}): worst normwise {w['norm']:.2e}, "
+          f"entrywise {w['entry']:.2e}")

@@ -42,10 +42,22 @@ def test_argument_errors():
         find.Plan(4, 4, 5, leaf=-1)
     with pytest.raises(find.FindError):
         find.Plan(4, 4, 5, symmetric=3)
-    # fronts beyond the kernels' 2048 nodes are refused at plan creation
+    # fronts beyond the kernels' 4096 nodes are refused at plan creation; those
+    # beyond 2048 take the eight-wave form (configuration 7) only
     with pytest.raises(find.FindError) as ei:
-        find.Plan(1024, 256, 9)
+        find.Plan(2100, 2, 5)
     assert ei.value.status == find.FIND_E_UNSUPPORTED
+    p = find.Plan(1030, 2, 5)
+    assert p.summary()["max_n"] > 2048
+    ex = p.export()
+    tiles, options = p.tiles(), p.tile_options()
+    big = 0
+    for k, (first, count, phase, variant) in enumerate(ex["stages"]):
+        n = max(int(e[3]) for e in ex["elims"][first:first + count])
+        if n > 2048:
+            assert options[k] == [7] and tiles[k] == 7, (k, n, options[k], tiles[k])
+            big += 1
+    assert big > 0
     with pytest.raises(find.FindError) as ei:
         find.Plan(4097, 4097, 5)
     assert ei.value.status == find.FIND_E_UNSUPPORTED

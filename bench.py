@@ -29,8 +29,8 @@ PRECISION = {"fp64": 0, "mixed": 1, "mixed-gless": 2}   # find_precision values
 # solve, from rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs (calibrated on a
 # plain copy; profiles/elim_kernels_c3_128x128_fp64.md).  Valid only for the
 # native sources (kernels, plan, C-ABI) they were measured on.
-TRAFFIC_BYTES_PER_LAUNCH = 18723860648.67
-TRAFFIC_KERNEL_SHA = "d06183293bf2b226"
+TRAFFIC_BYTES_PER_LAUNCH = 18726485274.62
+TRAFFIC_KERNEL_SHA = "2ef10f79e83a5292"
 TRAFFIC_TILES = "44451066360010555800"
 TRAFFIC_FORM = (0, 2)   # (symmetric form, energy groups) of the counter runs
 

@@ -29,9 +29,9 @@ PRECISION = {"fp64": 0, "mixed": 1, "mixed-gless": 2}   # find_precision values
 # solve, from rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs (calibrated on a
 # plain copy; profiles/elim_kernels_c3_128x128_fp64.md).  Valid only for the
 # native sources (kernels, plan, C-ABI) they were measured on.
-TRAFFIC_BYTES_PER_LAUNCH = 18726485274.62
-TRAFFIC_KERNEL_SHA = "2ef10f79e83a5292"
-TRAFFIC_TILES = "44451066360010555800"
+TRAFFIC_BYTES_PER_LAUNCH = 15482132043.16
+TRAFFIC_KERNEL_SHA = "8e3b8f814ac0cd5f"
+TRAFFIC_TILES = "445510763600105141418000"
 TRAFFIC_FORM = (0, 2)   # (symmetric form, energy groups) of the counter runs
 
 

@@ -77,6 +77,48 @@ struct Builder {
   int64_t slot(int64_t b) const { return block_elems(b, P.pack & 1) + block_elems(b, P.pack & 2); }
   std::vector<std::pair<int64_t, int64_t>> slot_size;   // (provisional offset, elements) per slot
 
+  // Split stages whose fronts differ widely in size.  At the tree levels that
+  // touch a contact column, the dense contact coupling puts the whole column
+  // into the boundary sets of the clusters next to it, so a few large fronts
+  // share a stage with many small interior ones; a stage's launch
+  // configuration is sized for its largest front.  The eliminations of a stage
+  // are independent, so the stage becomes consecutive sub-stages by front
+  // size class (at most 128, 256, 512, ... nodes), a class of fewer than
+  // kMinSplit fronts joining the next larger one.  Final leaf blocks are not
+  // split.
+  void split_stages() {
+    constexpr int kMinSplit = 16, kClasses = 6;
+    auto cls = [](int n) { int c = 0; while (c < kClasses - 1 && n > (128 << c)) ++c; return c; };
+    std::vector<Stage> out;
+    for (const Stage& st : P.stages) {
+      if (st.phase == PH_FINAL || st.count < 2 * kMinSplit) { out.push_back(st); continue; }
+      int count[kClasses] = {0}, group_of[kClasses], groups = 0, acc = 0;
+      for (int k = st.first; k < st.first + st.count; ++k) ++count[cls(P.elims[k].n)];
+      for (int c = 0; c < kClasses; ++c) {
+        group_of[c] = groups;
+        acc += count[c];
+        if (acc >= kMinSplit) { ++groups; acc = 0; }
+      }
+      if (acc > 0) {   // a small trailing group joins the one before it
+        if (groups > 0)
+          for (int c = 0; c < kClasses; ++c)
+            if (group_of[c] == groups) group_of[c] = groups - 1;
+        if (groups == 0) groups = 1;
+      }
+      if (groups <= 1) { out.push_back(st); continue; }
+      std::vector<Elim> part;
+      for (int g = 0; g < groups; ++g) {
+        const int first = st.first + int(part.size());
+        for (int k = st.first; k < st.first + st.count; ++k)
+          if (group_of[cls(P.elims[k].n)] == g) part.push_back(P.elims[k]);
+        const int cnt = st.first + int(part.size()) - first;
+        if (cnt > 0) out.push_back({first, cnt, st.phase, st.variant});
+      }
+      std::copy(part.begin(), part.end(), P.elims.begin() + st.first);
+    }
+    P.stages = out;
+  }
+
   // Place the slots in the energy pool by lifetime.  A slot lives from the
   // stage that writes it to the last stage that reads it (stages in plan
   // order; a solve runs a subset of them, in the same order), and two slots
@@ -588,6 +630,7 @@ struct Builder {
       }
       P.stages.push_back({first, int(P.elims.size()) - first, PH_FINAL, v});
     }
+    split_stages();
     assign_pool();
     // size limits and flop model
     for (auto& st : P.stages)

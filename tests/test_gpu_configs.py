@@ -1,9 +1,10 @@
 """GPU parity of the configurations the benchmark and the serving loop run,
 and of inputs and error paths the other parity tests leave out:
 
-* the 128 x 128 workload in the benchmark's launch configuration (symmetric
-  form, two energy groups, the tuning table's stage tiles), diagonal outputs
-  and bond outputs, against the RGF oracle on sampled energies;
+* the 128 x 128 workload in the benchmark's launch configuration (general
+  form, one energy group, the tuning table's stage tiles), diagonal outputs
+  and bond outputs, against the RGF oracle on sampled energies, and the
+  symmetric forms (two energy groups) at the same energies;
 * the 512 x 512 9-point workload in its tuned launch configuration, FP64 and
   the G<-only mixed form, against RGF-oracle values stored for two energies
   (tests/golden/make_golden_c5.py);
@@ -49,16 +50,16 @@ def tuned(f, plan, key):
 
 
 def test_c3_benchmark_configuration_against_rgf():
-    """128 x 128, 256 energies, as bench.py runs it (general form, two energy
-    groups, tuned tiles), diagonal outputs (the benchmark's) and bond outputs;
-    five sampled energies against RGF.  The symmetric form at the same
-    energies, within its own bound."""
+    """128 x 128, 256 energies, as bench.py runs it (general form, one energy
+    group, tuned tiles), diagonal outputs (the benchmark's) and bond outputs;
+    five sampled energies against RGF.  The symmetric forms at the same
+    energies (two energy groups), within their own bounds."""
     f = find()
     prob = inputs.make_preset("c3_128x128")
     sample = [0, 61, 128, 190, 255]
     sub = {k: prob[k][sample] for k in ("energies", "sigma", "sigma_less")}
     ref = rgf.rgf_solve(128, 128, 5, prob["H"], sub["energies"], sub["sigma"], sub["sigma_less"], bonds=True)
-    plan = tuned(f, f.Plan(128, 128, 5, streams=2), "128x128/5/8/fp64/4m")
+    plan = tuned(f, f.Plan(128, 128, 5), "128x128/5/8/fp64/4m")
     for bonds in (False, True):
         out = f.run_problem(plan, prob, want_bonds=bonds)
         w = compare(out, ref, prob, bonds=bonds, energies=sample, label=f"c3 bench config bonds={bonds}")

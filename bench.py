@@ -29,8 +29,8 @@ PRECISION = {"fp64": 0, "mixed": 1, "mixed-gless": 2}   # find_precision values
 # solve, from rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs (calibrated on a
 # plain copy; profiles/elim_kernels_c3_128x128_fp64.md).  Valid only for the
 # native sources (kernels, plan, C-ABI) they were measured on.
-TRAFFIC_BYTES_PER_LAUNCH = 31466916416.49
-TRAFFIC_KERNEL_SHA = "8e3b8f814ac0cd5f"
+TRAFFIC_BYTES_PER_LAUNCH = 31466327871.02
+TRAFFIC_KERNEL_SHA = "3a1478b9a0f559b6"
 TRAFFIC_TILES = "445510763600105141418000"
 TRAFFIC_FORM = (0, 1)   # (symmetric form, energy groups) of the counter runs
 
@@ -266,6 +266,13 @@ def main() -> int:
     for _ in range(max(1, args.warmup)):
         eager_step()
     find.sync_status(plan, stream)
+    # elimination launches per step, counted on one profiled eager step (a
+    # captured graph replays the same launches)
+    plan.set_profiling(True)
+    eager_step()
+    torch.cuda.synchronize()
+    launches_per_step = plan.profile()[2]
+    plan.set_profiling(False)
     if args.no_graph:
         # the library records a HIP event pair around every stage launch
         plan.set_profiling(True)
@@ -336,7 +343,7 @@ def main() -> int:
                                                                  (args.symmetric, max(1, args.streams))),
                      "kernel": "k_stage + k_final (elimination kernels, all stage launches)",
                      "timing": "HIP events per stage launch" if args.no_graph else "HIP events around each graph replay",
-                     "launches": nl, "kernel_ms_per_step": kms / args.steps,
+                     "launches_per_step": launches_per_step, "kernel_ms_per_step": kms / args.steps,
                      "algorithmic_flops_per_step": kflops / args.steps,
                      # context: the plain dense-per-front FIND's work on the same tree per
                      # step, over the same kernel time (the rate this run delivers in

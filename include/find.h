@@ -278,13 +278,14 @@ const char* find_last_error(void);
 
 /* Instrumentation for roofline measurement.  While enabled, find_solve
  * records a HIP event pair on its stream around every elimination-stage
- * kernel launch (inside a captured hipGraph the pairs are part of the graph
- * and are re-recorded by every replay).  find_plan_profile waits for the
- * event pairs of the most recent find_solve (or of the latest replay of a
- * captured one) and returns their summed elapsed milliseconds, their
- * algorithmic flops (the find_plan_flops model for the eliminations and
- * energies each launch processed) and the launch count.  Any pointer
- * argument may be NULL. */
+ * kernel launch, or, with several energy groups (streams > 1), around each
+ * pass (inside a captured hipGraph the pairs are part of the graph and are
+ * re-recorded by every replay).  find_plan_profile waits for the event pairs
+ * of the most recent find_solve (or of the latest replay of a captured one)
+ * and returns their summed elapsed milliseconds, their algorithmic flops (the
+ * find_plan_flops model for the eliminations and energies each timed region
+ * processed) and the number of elimination-stage kernel launches the solve
+ * enqueued.  Any pointer argument may be NULL. */
 find_status find_plan_set_profiling(find_plan plan, int enable);
 find_status find_plan_profile(find_plan plan, double* kernel_ms, double* kernel_flops, int* launches);
 

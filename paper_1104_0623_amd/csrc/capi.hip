@@ -67,6 +67,7 @@ struct DevState {
   std::vector<hipEvent_t> ev;
   std::vector<double> ev_flops;
   size_t ev_used = 0;
+  int launch_count = 0;   // stage launches of the profiled solve
   // concurrent energy groups: one stream and join event per group, one fork event
   std::vector<hipStream_t> lane_st;
   std::vector<hipEvent_t> lane_ev;
@@ -672,7 +673,7 @@ find_status enqueue_solve(find_plan plan, DevState* d, const SolveBufs& b, int n
                           const double* sigma_less_d, double* diag_G, double* diag_Gless, double* bond_G,
                           double* bond_Gless, double* bond_J, hipStream_t st) {
   const int variant = (bond_G || bond_Gless || bond_J) ? 1 : 0;
-  if (b.profiling) d->ev_used = 0;  // the profile describes this solve
+  if (b.profiling) { d->ev_used = 0; d->launch_count = 0; }  // the profile describes this solve
   hipLaunchKernelGGL(k_fill_int, dim3((nE + 255) / 256), dim3(256), 0, st, b.status, nE, 0);
   HIPCHK(hipGetLastError());
   const int ec = b.ec, lanes = b.lanes;
@@ -732,6 +733,7 @@ find_status enqueue_solve(find_plan plan, DevState* d, const SolveBufs& b, int n
         }
         const hipError_t he = launch_stage_k(plan, d, int(k), a, o, plan->tiles[k], sg);
         if (he != hipSuccess) return fail(FIND_E_DEVICE, std::string("stage launch: ") + hipGetErrorString(he));
+        if (b.profiling) ++d->launch_count;
         if (prof) {
           HIPCHK(hipEventRecord(d->ev[2 * d->ev_used + 1], sg));
           ++d->ev_used;
@@ -967,8 +969,8 @@ find_status find_plan_profile(find_plan plan, double* kernel_ms, double* kernel_
       HIPCHK(hipEventElapsedTime(&t, d.ev[2 * k], d.ev[2 * k + 1]));
       ms += t;
       fl += d.ev_flops[k];
-      ++nl;
     }
+    nl += d.launch_count;
   }
   if (kernel_ms) *kernel_ms = ms;
   if (kernel_flops) *kernel_flops = fl;

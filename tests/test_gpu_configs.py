@@ -365,3 +365,22 @@ def test_fronts_beyond_2048_nodes(Nx, Ny, ref_kind):
     w = compare(out, ref, prob, label=f"{Nx}x{Ny} fronts > 2048")
     print(f"{Nx}x{Ny} (largest front {plan.summary()['max_n']}): worst normwise {w['norm']:.2e}, "
           f"entrywise {w['entry']:.2e}")
+
+
+def test_profiling_counts_launches_and_flops():
+    """find_plan_profile: every elimination-stage launch of a solve is counted
+    (one per stage of the solved variant, per energy group and pass), and the
+    timed flops are the find_plan_flops model for the energies solved."""
+    f = find()
+    E = np.array([0.41 + 1e-6j, -2.9 + 1e-6j, 1.3 + 1e-3j, 0.2 + 1e-6j])
+    prob = inputs.make_problem(40, 24, 5, vmax=1.0, seed=7, energies=E, fL=1.0, fR=0.3)
+    for kw, groups in ((dict(), 1), (dict(streams=2), 2), (dict(max_energies=2), 2)):
+        plan = f.Plan(40, 24, 5, leaf=4, **kw)
+        stages = [s for s in plan.export()["stages"] if s[3] in (-1, 0) and s[1] > 0]
+        plan.set_profiling(True)
+        f.run_problem(plan, prob, want_bonds=False)
+        ms, fl, n = plan.profile()
+        plan.set_profiling(False)
+        assert n == groups * len(stages), (kw, n, len(stages))
+        assert ms > 0
+        assert abs(fl - plan.flops_per_energy() * E.size) <= 1e-9 * fl, kw

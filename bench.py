@@ -232,12 +232,10 @@ def main() -> int:
     table = json.load(open(os.path.join(ROOT, "paper_1104_0623_amd", "tuning.json")))
     tiles_from = "autotune"
     if args.scattering:
-        # the tree and fronts are those of the contacts-only plan: its tuned
-        # tiles unless a scattering entry exists
-        if key + "/scat" in table:
-            key += "/scat"
-        if not args.tiles and not args.no_autotune and key not in table:
-            args.no_autotune = True
+        # every node carries Sigma<: the final blocks' R_K support differs from
+        # the contacts-only plan's, so scattering plans have entries of their
+        # own (tuned on the spot when there is none)
+        key += "/scat"
     if not args.tiles and not args.autotune and not args.no_autotune and key in table:
         args.tiles, tiles_from = table[key], "tuning table"
     if args.tiles:

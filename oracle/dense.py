@@ -48,6 +48,31 @@ def hamiltonian_matrix(Nx: int, Ny: int, H: np.ndarray) -> np.ndarray:
     return Hm
 
 
+def bond_matrix(Nx: int, Ny: int, B: np.ndarray) -> np.ndarray:
+    """Dense n x n matrix of a stencil-pattern (bond) self-energy: B has the
+    layout of H's bond planes with two values per bond, B[k-1, y, x, 0] the
+    entry (i, j) and B[k-1, y, x, 1] the entry (j, i) for the bond of plane k
+    at (x, y) (i its first node, j its second, as in hamiltonian_matrix)."""
+    nb = B.shape[0]
+    n = Nx * Ny
+    M = np.zeros((n, n), dtype=np.complex128)
+    for y in range(Ny):
+        for x in range(Nx):
+            i = node(x, y, Nx)
+            pairs = []
+            if x + 1 < Nx:
+                pairs.append((0, i, node(x + 1, y, Nx)))
+            if y + 1 < Ny:
+                pairs.append((1, i, node(x, y + 1, Nx)))
+            if nb == 4 and x + 1 < Nx and y + 1 < Ny:
+                pairs.append((2, i, node(x + 1, y + 1, Nx)))
+                pairs.append((3, node(x + 1, y, Nx), node(x, y + 1, Nx)))
+            for k, a, b in pairs:
+                M[a, b] += B[k, y, x, 0]
+                M[b, a] += B[k, y, x, 1]
+    return M
+
+
 def contact_columns(Nx: int, Ny: int) -> list[np.ndarray]:
     """Global node indices of the left (y=0) and right (y=Ny-1) columns."""
     xs = np.arange(Nx)
@@ -71,9 +96,12 @@ def dense_A(Nx: int, Ny: int, H: np.ndarray, E: complex, sigma_e: np.ndarray) ->
 
 def dense_solve(Nx: int, Ny: int, stencil: int, H: np.ndarray, energies, sigma: np.ndarray,
                 sigma_less: np.ndarray, bonds: bool = True, keep_G: bool = False,
-                sigma_d: np.ndarray | None = None, sigma_less_d: np.ndarray | None = None) -> dict:
+                sigma_d: np.ndarray | None = None, sigma_less_d: np.ndarray | None = None,
+                sigma_b: np.ndarray | None = None, sigma_less_b: np.ndarray | None = None) -> dict:
     """Per energy: G = inv(A); G< = G Sigma< G^dagger (with the diagonal
-    scattering terms sigma_d, sigma_less_d when given).
+    scattering terms sigma_d, sigma_less_d, and the stencil-pattern ones
+    sigma_b, sigma_less_b ([nE][nst-1][Ny][Nx][2], see bond_matrix), when
+    given: A = E I - H - Sigma_L - Sigma_R - diag(sigma_d) - Sigma_b).
 
     Returns diag_G, diag_Gless ([nE][Ny][Nx] complex) and, if ``bonds``,
     bond_G = G_ij, bond_Gless = G<_ij and bond_J = 2 Re(H_ij G<_ji) for every
@@ -102,6 +130,10 @@ def dense_solve(Nx: int, Ny: int, stencil: int, H: np.ndarray, energies, sigma: 
             A -= np.diag(sigma_d[e].reshape(n))
         if sigma_less_d is not None:
             Sl += np.diag(sigma_less_d[e].reshape(n))
+        if sigma_b is not None:
+            A -= bond_matrix(Nx, Ny, sigma_b[e])
+        if sigma_less_b is not None:
+            Sl += bond_matrix(Nx, Ny, sigma_less_b[e])
         G = np.linalg.inv(A)
         Gl = G @ Sl @ G.conj().T
         out["diag_G"][e] = np.diag(G).reshape(Ny, Nx)

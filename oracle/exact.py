@@ -75,6 +75,36 @@ def h_value(H, Nx: int, Ny: int, i: int, j: int) -> Fraction:
     return Fraction(0)
 
 
+def bond_sigma_value(B, Nx: int, Ny: int, i: int, j: int) -> Q:
+    """Entry (i, j) of a stencil-pattern self-energy given per bond plane with
+    two values per bond (index 0: from the bond's first node to its second,
+    index 1: back), found from the displacement between the two nodes."""
+    if B is None:
+        return Q()
+    xi, yi = coords(i, Nx)
+    xj, yj = coords(j, Nx)
+    dx, dy = xj - xi, yj - yi
+    nb = len(B)
+    if (dx, dy) == (1, 0):
+        return Q.of(B[0][yi][xi][0])
+    if (dx, dy) == (-1, 0):
+        return Q.of(B[0][yj][xj][1])
+    if (dx, dy) == (0, 1):
+        return Q.of(B[1][yi][xi][0])
+    if (dx, dy) == (0, -1):
+        return Q.of(B[1][yj][xj][1])
+    if nb == 4:
+        if (dx, dy) == (1, 1):
+            return Q.of(B[2][yi][xi][0])
+        if (dx, dy) == (-1, -1):
+            return Q.of(B[2][yj][xj][1])
+        if (dx, dy) == (-1, 1):   # first node i = (x+1, y), second j = (x, y+1), x = xj
+            return Q.of(B[3][yi][xj][0])
+        if (dx, dy) == (1, -1):   # i = (x, y+1) is the second node, j = (x+1, y) the first, x = xi
+            return Q.of(B[3][yj][xi][1])
+    return Q()
+
+
 def contact_value(S, Nx: int, Ny: int, i: int, j: int) -> Q:
     """Entry (i, j) of the dense contact matrix: S[c][xi][xj] when both nodes
     sit on contact column c (left y = 0, right y = Ny-1)."""
@@ -103,20 +133,24 @@ def exact_inverse(M):
     return [row[n:] for row in A]
 
 
-def exact_solve(Nx: int, Ny: int, H, E, sigma_e, sless_e, bond_pairs):
+def exact_solve(Nx: int, Ny: int, H, E, sigma_e, sless_e, bond_pairs, sb_e=None, slb_e=None):
     """Exact diag G, diag G<, and (G_ij, G<_ij, J) for each (i, j) in
-    ``bond_pairs`` at one energy.  Returns python complex / float values."""
+    ``bond_pairs`` at one energy, with the stencil-pattern self-energies
+    sb_e, slb_e ([nst-1][Ny][Nx][2]) when given.  Returns python complex /
+    float values."""
     n = Nx * Ny
     Eq = Q.of(E)
     A = [[ZERO] * n for _ in range(n)]
     for i in range(n):
         for j in range(n):
-            v = Q(-h_value(H, Nx, Ny, i, j), 0) - contact_value(sigma_e, Nx, Ny, i, j)
+            v = (Q(-h_value(H, Nx, Ny, i, j), 0) - contact_value(sigma_e, Nx, Ny, i, j)
+                 - bond_sigma_value(sb_e, Nx, Ny, i, j))
             if i == j:
                 v = v + Eq
             A[i][j] = v
     G = exact_inverse(A)
-    S = [[contact_value(sless_e, Nx, Ny, i, j) for j in range(n)] for i in range(n)]
+    S = [[contact_value(sless_e, Nx, Ny, i, j) + bond_sigma_value(slb_e, Nx, Ny, i, j) for j in range(n)]
+         for i in range(n)]
 
     def gless(a, b):
         acc = Q()

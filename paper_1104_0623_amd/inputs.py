@@ -146,6 +146,30 @@ def scattering_self_energies_varied(Nx: int, Ny: int, nE: int, gamma: float = 0.
     return (s - 0.5j * g).astype(np.complex128), (1j * f * g).astype(np.complex128)
 
 
+def bond_scattering_self_energies(Nx: int, Ny: int, stencil: int, nE: int, scale: float = 0.02,
+                                  f: float = 0.5, symmetric: bool = False,
+                                  seed: int = 0) -> tuple[np.ndarray, np.ndarray]:
+    """Stencil-pattern (nearest-neighbour) scattering self-energies, laid out
+    like H's bond planes with two values per bond: [nE][nst-1][Ny][Nx][2],
+    index 0 the entry from the bond's first node to its second, index 1 the
+    entry back (nst = 3 for the 5-point, 5 for the 9-point stencil; entries
+    of bonds that leave the mesh are ignored).  Sigma_b = (a - i b) scale with
+    a ~ U[-1, 1], b ~ U[0, 1] per entry and energy (seeded; the two directions
+    equal with ``symmetric``, so that A stays complex symmetric), and
+    Sigma<_b = -f (Sigma_b - Sigma_b^dagger), i.e. entry (i, j) is
+    -f (Sigma_ij - conj(Sigma_ji))."""
+    rng = np.random.default_rng(seed)
+    nb = 2 if stencil == 5 else 4
+    shape = (nE, nb, Ny, Nx, 2)
+    sb = scale * (rng.uniform(-1.0, 1.0, size=shape) - 1j * rng.uniform(0.0, 1.0, size=shape))
+    if symmetric:
+        sb[..., 1] = sb[..., 0]
+    sl = np.empty_like(sb)
+    sl[..., 0] = -f * (sb[..., 0] - np.conj(sb[..., 1]))
+    sl[..., 1] = -f * (sb[..., 1] - np.conj(sb[..., 0]))
+    return sb.astype(np.complex128), sl.astype(np.complex128)
+
+
 def general_contact_perturbation(nE: int, Nx: int, scale: float, seed: int = 0) -> np.ndarray:
     """A seeded complex perturbation [nE][2][Nx][Nx] with no symmetry
     (entries (a + i b) * scale, a, b ~ U[-1, 1]); added to the lead

@@ -215,3 +215,60 @@ def test_scattering_self_energy_shift_and_identity():
                            sigma_d=sd, sigma_less_d=sl * 1.5)
     G, Gl = d2["G"][0], d2["Gless"][0]
     assert rel(-f * (G - G.conj().T), Gl + 2j * eta * f * (G @ G.conj().T)) > 1e-3
+
+
+@pytest.mark.parametrize("Nx,Ny,stencil,seed,E", TINY[:4])
+def test_bond_scattering_dense_matches_exact(Nx, Ny, stencil, seed, E):
+    """Stencil-pattern scattering self-energies: the dense oracle (bond
+    planes embedded by bond enumeration) against the exact brute force
+    (entries found from node displacements), with no symmetry between the
+    two directions of a bond; a swap of the directions fails."""
+    p = problem(Nx, Ny, stencil, seed, E)
+    sb, sl = inputs.bond_scattering_self_energies(Nx, Ny, stencil, 1, scale=0.05, f=0.3, seed=seed + 11)
+    sl = sl + 0.01 * sb   # a Sigma< with no relation to Sigma_b
+    d = dense.dense_solve(Nx, Ny, stencil, p["H"], p["energies"], p["sigma"], p["sigma_less"],
+                          sigma_b=sb, sigma_less_b=sl)
+    bi, bj, _, _ = inputs.bond_endpoints(Nx, Ny, stencil)
+    dG, dGl, bonds = exact.exact_solve(Nx, Ny, p["H"], E, p["sigma"][0], p["sigma_less"][0],
+                                       list(zip(bi.tolist(), bj.tolist())), sb[0], sl[0])
+    assert rel(d["diag_G"][0].ravel(), dG) < 1e-12
+    assert rel(d["diag_Gless"][0].ravel(), dGl) < 1e-12
+    if bonds:
+        assert rel(d["bond_G"][0], np.array([b[0] for b in bonds])) < 1e-12
+        assert rel(d["bond_Gless"][0], np.array([b[1] for b in bonds])) < 1e-12
+    swapped = dense.dense_solve(Nx, Ny, stencil, p["H"], p["energies"], p["sigma"], p["sigma_less"],
+                                sigma_b=sb[..., ::-1].copy(), sigma_less_b=sl[..., ::-1].copy())
+    if bonds:
+        assert rel(swapped["bond_G"][0], np.array([b[0] for b in bonds])) > 1e-6
+
+
+def test_bond_scattering_hopping_shift_and_equilibrium():
+    """A real symmetric stencil-pattern Sigma_b = c H (on every bond, both
+    directions) is the hopping rescaling H_ij -> (1 + c) H_ij (A = E - H -
+    Sigma); and with
+    Sigma<_b = -f (Sigma_b - Sigma_b^dagger), the same f as the contacts', the
+    eta-corrected equilibrium identity -f (G - G^dagger) =
+    G Sigma< G^dagger + 2 i eta f G G^dagger holds."""
+    Nx, Ny, f, eta, c = 5, 6, 0.35, 1e-3, 0.07
+    E = np.array([0.4 + 1j * eta, -1.3 + 1j * eta])
+    for stencil in (5, 9):
+        p = inputs.make_problem(Nx, Ny, stencil, vmax=0.6, seed=3, energies=E, fL=f, fR=f)
+        H = p["H"]
+        nb = H.shape[0] - 1
+        sb = np.zeros((E.size, nb, Ny, Nx, 2), np.complex128)
+        for k in range(nb):
+            sb[:, k, :, :, 0] = sb[:, k, :, :, 1] = c * H[k + 1]
+        a = dense.dense_solve(Nx, Ny, stencil, H, E, p["sigma"], p["sigma_less"], sigma_b=sb,
+                              sigma_less_b=np.zeros_like(sb))
+        H2 = H.copy()
+        H2[1:] *= 1.0 + c
+        b = dense.dense_solve(Nx, Ny, stencil, H2, E, p["sigma"], p["sigma_less"])
+        for k in ("diag_G", "diag_Gless", "bond_G", "bond_Gless"):
+            assert rel(a[k], b[k]) < 1e-12, (stencil, k)
+        sb, sl = inputs.bond_scattering_self_energies(Nx, Ny, stencil, E.size, scale=0.04, f=f, seed=5)
+        d = dense.dense_solve(Nx, Ny, stencil, H, E, p["sigma"], p["sigma_less"], keep_G=True,
+                              sigma_b=sb, sigma_less_b=sl)
+        for e in range(E.size):
+            G, Gl = d["G"][e], d["Gless"][e]
+            assert rel(-f * (G - G.conj().T), Gl + 2j * eta * f * (G @ G.conj().T)) < 1e-11
+            assert rel(Gl, -Gl.conj().T) < 1e-12

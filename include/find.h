@@ -242,6 +242,28 @@ find_status find_solve_scattering(find_plan plan, int nE, const double* energies
                                   const double* sigma_less_d, double* diag_G, double* diag_Gless,
                                   double* bond_G, double* bond_Gless, double* bond_J, void* hip_stream);
 
+/* find_solve_scattering with, in addition, stencil-pattern (nearest-
+ * neighbour) scattering self-energies, the general form of a local
+ * self-energy (paper §1: the scattering self-energy is often, not always,
+ * diagonal): A = E I - H - Sigma_L - Sigma_R - diag(Sigma_d) - Sigma_b and
+ * Sigma< = ... + diag(Sigma<_d) + Sigma<_b.  sigma_b and sigma_less_b are
+ * complex device arrays [nE][nst-1][Ny][Nx][2] laid out like H's bond planes
+ * (plane k = 1 .. nst-1 of H is plane k-1 here) with two values per bond:
+ * [..][y][x][0] is the entry (i, j) from the bond's first node i to its second
+ * node j, [..][y][x][1] the entry (j, i) (the bond of H plane k at (x, y), as
+ * described for H; entries of bonds that leave the mesh are not read).  For
+ * the symmetric forms Sigma_b must be symmetric (equal entries for both
+ * directions) and Sigma<_b anti-Hermitian.  bond_J stays 2 Re(H_ij G<_ji)
+ * (the coherent part of the current).  Requires a scattering plan; every
+ * pointer but the optional bond outputs must be non-NULL (zero arrays for an
+ * absent diagonal part).  Other arguments and errors as
+ * find_solve_scattering. */
+find_status find_solve_scattering_bonds(find_plan plan, int nE, const double* energies, const double* H,
+                                        const double* sigma, const double* sigma_less, const double* sigma_d,
+                                        const double* sigma_less_d, const double* sigma_b,
+                                        const double* sigma_less_b, double* diag_G, double* diag_Gless,
+                                        double* bond_G, double* bond_Gless, double* bond_J, void* hip_stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, serving loops or harnesses that forbid hipMalloc): find_solve for
  * a contacts-only plan with every scratch buffer of the solve (energy pool,

@@ -608,7 +608,8 @@ find_status prepare(find_plan_s* plan, int nE, hipStream_t st, DevState** dout, 
 void pass_args(const find_plan_s* plan, const DevState* d, int variant, int e0, int ne, const double* energies,
                const double* H, const double* sigma, const double* sigma_less, double* diag_G,
                double* diag_Gless, double* bond_G, double* bond_Gless, double* bond_J, StageArgs* pa,
-               OutArgs* po, const double* sigma_d = nullptr, const double* sigma_less_d = nullptr) {
+               OutArgs* po, const double* sigma_d = nullptr, const double* sigma_less_d = nullptr,
+               const double* sigma_b = nullptr, const double* sigma_less_b = nullptr) {
   const Plan& P = plan->P;
   const size_t nx2 = size_t(P.Nx) * P.Nx;
   const size_t nnodes = size_t(P.Nx) * P.Ny;
@@ -621,6 +622,10 @@ void pass_args(const find_plan_s* plan, const DevState* d, int variant, int e0, 
   a.sless = sigma_less ? reinterpret_cast<const double2*>(sigma_less) + size_t(e0) * 2 * nx2 : nullptr;
   a.sscat = sigma_d ? reinterpret_cast<const double2*>(sigma_d) + size_t(e0) * nnodes : nullptr;
   a.slscat = sigma_less_d ? reinterpret_cast<const double2*>(sigma_less_d) + size_t(e0) * nnodes : nullptr;
+  // stencil-pattern scattering: [nE][nst-1][Ny][Nx][2] complex per energy
+  const size_t bstride = size_t(P.stencil == 9 ? 4 : 2) * nnodes * 2;
+  a.sbond = sigma_b ? reinterpret_cast<const double2*>(sigma_b) + size_t(e0) * bstride : nullptr;
+  a.slbond = sigma_less_b ? reinterpret_cast<const double2*>(sigma_less_b) + size_t(e0) * bstride : nullptr;
   a.onsite_off = P.onsite_off;
   a.pool = d->pool; a.pool_stride = P.pool_per_energy;
   a.ws = d->ws;   // (an energy group of a multi-stream pass offsets this)
@@ -671,7 +676,8 @@ struct SolveBufs {
 find_status enqueue_solve(find_plan plan, DevState* d, const SolveBufs& b, int nE, const double* energies,
                           const double* H, const double* sigma, const double* sigma_less, const double* sigma_d,
                           const double* sigma_less_d, double* diag_G, double* diag_Gless, double* bond_G,
-                          double* bond_Gless, double* bond_J, hipStream_t st) {
+                          double* bond_Gless, double* bond_J, hipStream_t st, const double* sigma_b = nullptr,
+                          const double* sigma_less_b = nullptr) {
   const int variant = (bond_G || bond_Gless || bond_J) ? 1 : 0;
   if (b.profiling) { d->ev_used = 0; d->launch_count = 0; }  // the profile describes this solve
   hipLaunchKernelGGL(k_fill_int, dim3((nE + 255) / 256), dim3(256), 0, st, b.status, nE, 0);
@@ -708,7 +714,7 @@ find_status enqueue_solve(find_plan plan, DevState* d, const SolveBufs& b, int n
       StageArgs a;
       OutArgs o;
       pass_args(plan, d, variant, g0, gn, energies, H, sigma, sigma_less, diag_G, diag_Gless, bond_G, bond_Gless,
-                bond_J, &a, &o, sigma_d, sigma_less_d);
+                bond_J, &a, &o, sigma_d, sigma_less_d, sigma_b, sigma_less_b);
       a.ws = b.ws + size_t(g) * lws;
       a.pool = b.pool + size_t(g0 - e0) * size_t(plan->P.pool_per_energy);   // kernels index energies from 0
       a.status = b.status + g0;
@@ -755,12 +761,14 @@ find_status enqueue_solve(find_plan plan, DevState* d, const SolveBufs& b, int n
   return FIND_OK;
 }
 
-// The solve of find_solve and find_solve_scattering (sigma_d and sigma_less_d
-// NULL for the former) in the plan's own buffers; arguments checked by the callers.
+// The solve of find_solve and find_solve_scattering(_bonds) (the scattering
+// arrays NULL where absent) in the plan's own buffers; arguments checked by
+// the callers.
 find_status solve_impl(find_plan plan, int nE, const double* energies, const double* H, const double* sigma,
                        const double* sigma_less, const double* sigma_d, const double* sigma_less_d,
                        double* diag_G, double* diag_Gless,
-                       double* bond_G, double* bond_Gless, double* bond_J, void* hip_stream) {
+                       double* bond_G, double* bond_Gless, double* bond_J, void* hip_stream,
+                       const double* sigma_b = nullptr, const double* sigma_less_b = nullptr) {
   std::lock_guard<std::mutex> lk(plan->mu);
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   plan->last_status = nullptr;
@@ -772,7 +780,7 @@ find_status solve_impl(find_plan plan, int nE, const double* energies, const dou
   const int lanes = lanes_of(plan);
   const SolveBufs b{d->pool, d->ws, d->status, ec, lanes, lane_ws(*d, ec, lanes), plan->profiling};
   return enqueue_solve(plan, d, b, nE, energies, H, sigma, sigma_less, sigma_d, sigma_less_d, diag_G, diag_Gless,
-                       bond_G, bond_Gless, bond_J, st);
+                       bond_G, bond_Gless, bond_J, st, sigma_b, sigma_less_b);
 }
 
 }  // namespace
@@ -805,6 +813,22 @@ find_status find_solve_scattering(find_plan plan, int nE, const double* energies
     return fail(FIND_E_ARG, "find_solve_scattering: the plan was created without opts.scattering");
   return solve_impl(plan, nE, energies, H, sigma, sigma_less, sigma_d, sigma_less_d, diag_G, diag_Gless, bond_G,
                     bond_Gless, bond_J, hip_stream);
+}
+
+find_status find_solve_scattering_bonds(find_plan plan, int nE, const double* energies, const double* H,
+                                        const double* sigma, const double* sigma_less, const double* sigma_d,
+                                        const double* sigma_less_d, const double* sigma_b,
+                                        const double* sigma_less_b, double* diag_G, double* diag_Gless,
+                                        double* bond_G, double* bond_Gless, double* bond_J, void* hip_stream) {
+  if (!plan) return fail(FIND_E_ARG, "find_solve_scattering_bonds: NULL plan");
+  if (nE < 1) return fail(FIND_E_ARG, "find_solve_scattering_bonds: nE must be >= 1");
+  if (!energies || !H || !sigma_d || !sigma_less_d || !sigma_b || !sigma_less_b || !diag_G || !diag_Gless ||
+      (plan->P.contacts && (!sigma || !sigma_less)))
+    return fail(FIND_E_ARG, "find_solve_scattering_bonds: NULL input or diagonal output pointer");
+  if (!plan->opts.scattering)
+    return fail(FIND_E_ARG, "find_solve_scattering_bonds: the plan was created without opts.scattering");
+  return solve_impl(plan, nE, energies, H, sigma, sigma_less, sigma_d, sigma_less_d, diag_G, diag_Gless, bond_G,
+                    bond_Gless, bond_J, hip_stream, sigma_b, sigma_less_b);
 }
 
 find_status find_solve_noalloc(find_plan plan, int nE, const double* energies, const double* H,

@@ -69,38 +69,72 @@ struct Orig {
   int Nx, Ny, nst;
   int scat;             // 1: diagonal scattering self-energies present (Sigma<_d read from D)
   int contacts;         // 1: contact self-energies on the columns y = 0 and y = Ny - 1
+  // stencil-pattern scattering self-energies of this energy, laid out like
+  // H's bond planes with two values per bond ([nst-1][Ny][Nx][2]: from the
+  // bond's first node to its second, then back), or NULL
+  const double2* sb;
+  const double2* slb;
 
-  // H_ij for i = (xi, yi), j = (xj, yj), i != j
-  __device__ double hval(int xi, int yi, int xj, int yj) const {
+  // The bond between i = (xi, yi) and j = (xj, yj), i != j: its plane k of H
+  // (1 .. nst-1; 0 if the nodes are not stencil neighbours), the index of its
+  // entry in the plane, and whether i is the bond's first node.
+  __device__ int bond(int xi, int yi, int xj, int yj, int& idx, bool& fwd) const {
     const int dx = xj - xi, dy = yj - yi;
-    const int plane = Nx * Ny;
-    if (dy == 0) return dx == 1 ? H[plane + yi * Nx + xi] : dx == -1 ? H[plane + yj * Nx + xj] : 0.0;
-    if (dx == 0) return dy == 1 ? H[2 * plane + yi * Nx + xi] : dy == -1 ? H[2 * plane + yj * Nx + xj] : 0.0;
-    if (nst == 5) {
-      if (dx == 1 && dy == 1) return H[3 * plane + yi * Nx + xi];
-      if (dx == -1 && dy == -1) return H[3 * plane + yj * Nx + xj];
-      if (dx == -1 && dy == 1) return H[4 * plane + yi * Nx + xj];  // i=(x+1,y), j=(x,y+1)
-      if (dx == 1 && dy == -1) return H[4 * plane + yj * Nx + xi];  // i=(x,y+1), j=(x+1,y)
+    fwd = true;
+    if (dy == 0) {
+      if (dx == 1) { idx = yi * Nx + xi; return 1; }
+      if (dx == -1) { idx = yj * Nx + xj; fwd = false; return 1; }
+      return 0;
     }
-    return 0.0;
+    if (dx == 0) {
+      if (dy == 1) { idx = yi * Nx + xi; return 2; }
+      if (dy == -1) { idx = yj * Nx + xj; fwd = false; return 2; }
+      return 0;
+    }
+    if (nst == 5) {
+      if (dx == 1 && dy == 1) { idx = yi * Nx + xi; return 3; }
+      if (dx == -1 && dy == -1) { idx = yj * Nx + xj; fwd = false; return 3; }
+      if (dx == -1 && dy == 1) { idx = yi * Nx + xj; return 4; }                // i=(x+1,y) first, j=(x,y+1)
+      if (dx == 1 && dy == -1) { idx = yj * Nx + xi; fwd = false; return 4; }   // i=(x,y+1), j=(x+1,y) first
+    }
+    return 0;
+  }
+  // entry (i, j) of a bond self-energy array for the bond (k, idx, fwd)
+  __device__ double2 bond_value(const double2* b, int k, int idx, bool fwd) const {
+    return b[(((size_t)(k - 1) * Nx * Ny + idx) << 1) + (fwd ? 0 : 1)];
   }
   // A_ij
   __device__ double2 a(int xi, int yi, int xj, int yj) const {
     double2 av = zero2();
     const int dx = xj - xi, dy = yj - yi;
     if (dx == 0 && dy == 0) av = D[yi * Nx + xi];
-    else if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) av.x = -hval(xi, yi, xj, yj);
+    else if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) {
+      int idx;
+      bool fwd;
+      const int k = bond(xi, yi, xj, yj, idx, fwd);
+      if (k) {
+        av.x = -H[(size_t)k * Nx * Ny + idx];
+        if (sb) { const double2 t = bond_value(sb, k, idx, fwd); av.x -= t.x; av.y -= t.y; }
+      }
+    }
     if (contacts && dy == 0) {
       if (yi == 0) { const double2 t = sig[xi * Nx + xj]; av.x -= t.x; av.y -= t.y; }
       if (yi == Ny - 1) { const double2 t = sig[Nx * Nx + xi * Nx + xj]; av.x -= t.x; av.y -= t.y; }
     }
     return av;
   }
-  // Sigma<_ij (non-zero only between two nodes of one contact column, and on
-  // the diagonal with scattering self-energies)
+  // Sigma<_ij (non-zero only between two nodes of one contact column, and,
+  // with scattering self-energies, on the diagonal and between stencil
+  // neighbours)
   __device__ double2 s(int xi, int yi, int xj, int yj) const {
     double2 sv = zero2();
     if (scat && xi == xj && yi == yj) sv = D[Nx * Ny + yi * Nx + xi];
+    if (slb && (xi != xj || yi != yj)) {
+      int idx;
+      bool fwd;
+      const int k = bond(xi, yi, xj, yj, idx, fwd);
+      if (k) { const double2 u = bond_value(slb, k, idx, fwd); sv.x += u.x; sv.y += u.y; }
+    }
     if (contacts && yi == yj) {
       if (yi == 0) { const double2 u = sless[xi * Nx + xj]; sv.x += u.x; sv.y += u.y; }
       if (yi == Ny - 1) { const double2 u = sless[Nx * Nx + xi * Nx + xj]; sv.x += u.x; sv.y += u.y; }
@@ -825,7 +859,9 @@ __global__ __launch_bounds__(NT, (TC == kTileWg || NT == 512) ? 2 : 3) void k_st
     const Front fr{L.node, L.srcpos, pool + E.src0, pool + E.src1, E.ld0, E.ld1,
                    Orig{a.H, a.contacts ? a.sigma + (size_t)e * 2 * a.Nx * a.Nx : nullptr,
                         a.contacts ? a.sless + (size_t)e * 2 * a.Nx * a.Nx : nullptr,
-                        pool + a.onsite_off, a.Nx, a.Ny, a.nst, a.sscat != nullptr, a.contacts}, a.sym};
+                        pool + a.onsite_off, a.Nx, a.Ny, a.nst, a.sscat != nullptr, a.contacts,
+                        a.sbond ? a.sbond + (size_t)e * (a.nst - 1) * a.Nx * a.Ny * 2 : nullptr,
+                        a.slbond ? a.slbond + (size_t)e * (a.nst - 1) * a.Nx * a.Ny * 2 : nullptr}, a.sym};
     // 1. assemble the tall block [A_g(S,S); A_g(B,S)]; the other blocks of A_g
     //    and all of Sigma_g are gathered from their sources by the products
     double amax = 0.0;   // this thread's largest |re| + |im| in A_g(S,S)

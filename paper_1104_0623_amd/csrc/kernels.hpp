@@ -34,6 +34,8 @@ struct StageArgs {
   const double2* sless;
   const double2* sscat;   // diagonal scattering Sigma of this pass [nE][Ny][Nx], or NULL
   const double2* slscat;  // and Sigma< (read by the node-diagonal pre-pass only)
+  const double2* sbond;   // stencil-pattern scattering Sigma of this pass [nE][nst-1][Ny][Nx][2], or NULL
+  const double2* slbond;  // and Sigma<
   long long onsite_off;   // pool offset (per energy) of the node diagonal E - H_ii - Sigma_d,i, then Sigma<_d,i
   double2* pool;          // pool of this pass, energy stride pool_stride
   long long pool_stride;

@@ -24,6 +24,7 @@ EXPORTED = ["find_plan_create", "find_plan_destroy", "find_plan_footprint", "fin
             "find_n_bonds", "find_solve", "find_sync_status", "find_last_error",
             "find_plan_summary", "find_plan_export", "find_plan_set_profiling", "find_plan_profile",
             "find_plan_autotune", "find_plan_get_tiles", "find_plan_set_tiles", "find_solve_scattering",
+            "find_solve_scattering_bonds",
             "find_solve_noalloc"]
 
 
@@ -76,6 +77,8 @@ def lib() -> ctypes.CDLL:
         L.find_solve.restype = st
         L.find_solve_scattering.argtypes = [vp, i32] + [vp] * 11 + [vp]
         L.find_solve_scattering.restype = st
+        L.find_solve_scattering_bonds.argtypes = [vp, i32] + [vp] * 13 + [vp]
+        L.find_solve_scattering_bonds.restype = st
         L.find_solve_noalloc.argtypes = [vp, i32] + [vp] * 9 + [vp]
         L.find_solve_noalloc.restype = st
         L.find_sync_status.argtypes = [vp, vp]; L.find_sync_status.restype = st
@@ -208,17 +211,22 @@ def _ptr(t, name, shape, dtype):
 
 
 def solve(plan: Plan, energies, H, sigma, sigma_less, diag_G, diag_Gless,
-          bond_G=None, bond_Gless=None, bond_J=None, stream=None, sigma_d=None, sigma_less_d=None) -> None:
+          bond_G=None, bond_Gless=None, bond_J=None, stream=None, sigma_d=None, sigma_less_d=None,
+          sigma_b=None, sigma_less_b=None) -> None:
     """Enqueue one FIND solve on `stream` (default: torch's current stream).
 
     energies complex128 [nE]; H float64 [nst][Ny][Nx]; sigma, sigma_less complex128
     [nE][2][Nx][Nx]; diag_G, diag_Gless complex128 [nE][Ny][Nx]; optional
     bond_G, bond_Gless complex128 [nE][nbonds] and bond_J float64 [nE][nbonds].
     For a plan created with scattering=True, sigma_d and sigma_less_d complex128
-    [nE][Ny][Nx] (diagonal scattering self-energies) are required.
+    [nE][Ny][Nx] (diagonal scattering self-energies) are required, and
+    sigma_b, sigma_less_b complex128 [nE][nst-1][Ny][Nx][2] (stencil-pattern
+    scattering self-energies, find_solve_scattering_bonds) may be given.
     """
-    if not plan.scattering and (sigma_d is not None or sigma_less_d is not None):
-        raise ValueError("sigma_d / sigma_less_d given for a plan created without scattering=True")
+    if not plan.scattering and any(v is not None for v in (sigma_d, sigma_less_d, sigma_b, sigma_less_b)):
+        raise ValueError("scattering self-energies given for a plan created without scattering=True")
+    if (sigma_b is None) != (sigma_less_b is None):
+        raise ValueError("sigma_b and sigma_less_b go together")
     import torch
     Nx, Ny = plan.Nx, plan.Ny
     nE = int(energies.shape[0])
@@ -237,7 +245,12 @@ def solve(plan: Plan, energies, H, sigma, sigma_less, diag_G, diag_Gless,
         if sigma_d is None or sigma_less_d is None:
             raise ValueError("a scattering plan needs sigma_d and sigma_less_d")
         d = [_ptr(sigma_d, "sigma_d", (nE, Ny, Nx), c128), _ptr(sigma_less_d, "sigma_less_d", (nE, Ny, Nx), c128)]
-        _check(lib().find_solve_scattering(plan.handle, nE, *args[:4], *d, *args[4:], sp))
+        if sigma_b is not None:
+            bshape = (nE, nst - 1, Ny, Nx, 2)
+            b = [_ptr(sigma_b, "sigma_b", bshape, c128), _ptr(sigma_less_b, "sigma_less_b", bshape, c128)]
+            _check(lib().find_solve_scattering_bonds(plan.handle, nE, *args[:4], *d, *b, *args[4:], sp))
+        else:
+            _check(lib().find_solve_scattering(plan.handle, nE, *args[:4], *d, *args[4:], sp))
     else:
         _check(lib().find_solve(plan.handle, nE, *args, sp))
 
@@ -310,9 +323,9 @@ def run_problem(plan: Plan, prob: dict, want_bonds: bool = True, device: str = "
                    bond_Gless=torch.empty((nE, nb), dtype=torch.complex128, device=dev),
                    bond_J=torch.empty((nE, nb), dtype=torch.float64, device=dev))
     extra = {}
-    if "sigma_d" in prob:
-        extra = dict(sigma_d=torch.as_tensor(np.ascontiguousarray(prob["sigma_d"]), device=dev),
-                     sigma_less_d=torch.as_tensor(np.ascontiguousarray(prob["sigma_less_d"]), device=dev))
+    for k in ("sigma_d", "sigma_less_d", "sigma_b", "sigma_less_b"):
+        if k in prob:
+            extra[k] = torch.as_tensor(np.ascontiguousarray(prob[k]), device=dev)
     solve(plan, E, H, S, SL, out["diag_G"], out["diag_Gless"], out.get("bond_G"), out.get("bond_Gless"),
           out.get("bond_J"), **extra)
     sync_status(plan)

@@ -384,3 +384,30 @@ def test_profiling_counts_launches_and_flops():
         assert n == groups * len(stages), (kw, n, len(stages))
         assert ms > 0
         assert abs(fl - plan.flops_per_energy() * E.size) <= 1e-9 * fl, kw
+
+
+@pytest.mark.parametrize("Nx,Ny,stencil,leaf", [(16, 12, 5, 4), (13, 10, 9, 2), (20, 24, 5, 8), (12, 17, 9, 4)])
+def test_bond_scattering_against_dense(Nx, Ny, stencil, leaf):
+    """Stencil-pattern (nearest-neighbour) scattering self-energies on top of
+    diagonal ones that differ per energy and node: with no symmetry between
+    a bond's two directions in the general form, symmetric in the symmetric
+    form; against the dense oracle with bond outputs, in one pass and in
+    passes of two energies over two energy groups."""
+    f = find()
+    E = np.array([0.41 + 1e-6j, -1.9 + 1e-4j, 1.3 + 1e-3j])
+    prob = inputs.make_problem(Nx, Ny, stencil, vmax=1.0, seed=Nx * 7 + Ny, energies=E, fL=1.0, fR=0.3)
+    sd, sld = inputs.scattering_self_energies_varied(Nx, Ny, E.size, seed=Nx + Ny)
+    for sym in (0, 1):
+        sb, slb = inputs.bond_scattering_self_energies(Nx, Ny, stencil, E.size, scale=0.03, f=0.4,
+                                                        symmetric=bool(sym), seed=Nx * Ny + sym)
+        p = dict(prob, sigma_d=sd, sigma_less_d=sld, sigma_b=sb, sigma_less_b=slb)
+        ref = dense.dense_solve(Nx, Ny, stencil, prob["H"], E, prob["sigma"], prob["sigma_less"],
+                                sigma_d=sd, sigma_less_d=sld, sigma_b=sb, sigma_less_b=slb)
+        plain = dense.dense_solve(Nx, Ny, stencil, prob["H"], E, prob["sigma"], prob["sigma_less"],
+                                  sigma_d=sd, sigma_less_d=sld)
+        assert nrel(ref["diag_Gless"], plain["diag_Gless"]) > 1e-4   # the bond terms matter
+        for kw in ({}, dict(streams=2, max_energies=2)):
+            plan = f.Plan(Nx, Ny, stencil, leaf=leaf, scattering=True, symmetric=sym, **kw)
+            out = f.run_problem(plan, p, want_bonds=True)
+            w = compare(out, ref, p, tol=SYM_TOL if sym else TOL, label=f"bond scattering {Nx}x{Ny} sym={sym} {kw}")
+            print(f"bond scattering {Nx}x{Ny}/{stencil} sym={sym} {kw}: worst normwise {w['norm']:.2e}")

@@ -737,7 +737,12 @@ find_status enqueue_solve(find_plan plan, DevState* d, const SolveBufs& b, int n
           d->ev_flops[d->ev_used] = s2.flops_per_energy * gn;
           HIPCHK(hipEventRecord(d->ev[2 * d->ev_used], sg));
         }
-        const hipError_t he = launch_stage_k(plan, d, int(k), a, o, plan->tiles[k], sg);
+        // solves with stencil-pattern scattering self-energies take the 32x32
+        // wave tile (the eight-wave form where it is the only one), the
+        // configurations compiled with the bond reads
+        const int tck = (a.sbond && s2.phase != PH_FINAL) ? ((plan->tile_mask[k] & 1) ? 0 : kTileEight)
+                                                          : plan->tiles[k];
+        const hipError_t he = launch_stage_k(plan, d, int(k), a, o, tck, sg);
         if (he != hipSuccess) return fail(FIND_E_DEVICE, std::string("stage launch: ") + hipGetErrorString(he));
         if (b.profiling) ++d->launch_count;
         if (prof) {
@@ -827,6 +832,8 @@ find_status find_solve_scattering_bonds(find_plan plan, int nE, const double* en
     return fail(FIND_E_ARG, "find_solve_scattering_bonds: NULL input or diagonal output pointer");
   if (!plan->opts.scattering)
     return fail(FIND_E_ARG, "find_solve_scattering_bonds: the plan was created without opts.scattering");
+  if (plan->opts.complex_mode != FIND_CPLX_4M)
+    return fail(FIND_E_UNSUPPORTED, "find_solve_scattering_bonds: 4M complex products only");
   return solve_impl(plan, nE, energies, H, sigma, sigma_less, sigma_d, sigma_less_d, diag_G, diag_Gless, bond_G,
                     bond_Gless, bond_J, hip_stream, sigma_b, sigma_less_b);
 }

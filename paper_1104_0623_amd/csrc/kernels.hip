@@ -61,7 +61,11 @@ __device__ __forceinline__ double2 zero2() { return make_double2(0.0, 0.0); }
 
 // Entries of the original A = E I - H - Sigma_L - Sigma_R and of Sigma<,
 // addressed by node coordinates (x, y) (no integer division).
-struct Orig {
+// BONDS: the plan's solve passes stencil-pattern scattering self-energies
+// (compiled separately, so that the gathers of every other solve keep their
+// registers)
+template <bool BONDS>
+struct OrigT {
   const double* H;
   const double2* sig;
   const double2* sless;
@@ -71,7 +75,7 @@ struct Orig {
   int contacts;         // 1: contact self-energies on the columns y = 0 and y = Ny - 1
   // stencil-pattern scattering self-energies of this energy, laid out like
   // H's bond planes with two values per bond ([nst-1][Ny][Nx][2]: from the
-  // bond's first node to its second, then back), or NULL
+  // bond's first node to its second, then back); read only with BONDS
   const double2* sb;
   const double2* slb;
 
@@ -99,9 +103,28 @@ struct Orig {
     }
     return 0;
   }
-  // entry (i, j) of a bond self-energy array for the bond (k, idx, fwd)
-  __device__ double2 bond_value(const double2* b, int k, int idx, bool fwd) const {
-    return b[(((size_t)(k - 1) * Nx * Ny + idx) << 1) + (fwd ? 0 : 1)];
+  // entry (i, j) of a bond self-energy array (zero unless the nodes are
+  // stencil neighbours)
+  __device__ double2 bond_value(const double2* b, int xi, int yi, int xj, int yj) const {
+    int idx;
+    bool fwd;
+    const int k = bond(xi, yi, xj, yj, idx, fwd);
+    return k ? b[(((size_t)(k - 1) * Nx * Ny + idx) << 1) + (fwd ? 0 : 1)] : zero2();
+  }
+  // H_ij for i = (xi, yi), j = (xj, yj), i != j (the bond lookup above,
+  // written out with the plane offsets folded in)
+  __device__ double hval(int xi, int yi, int xj, int yj) const {
+    const int dx = xj - xi, dy = yj - yi;
+    const int plane = Nx * Ny;
+    if (dy == 0) return dx == 1 ? H[plane + yi * Nx + xi] : dx == -1 ? H[plane + yj * Nx + xj] : 0.0;
+    if (dx == 0) return dy == 1 ? H[2 * plane + yi * Nx + xi] : dy == -1 ? H[2 * plane + yj * Nx + xj] : 0.0;
+    if (nst == 5) {
+      if (dx == 1 && dy == 1) return H[3 * plane + yi * Nx + xi];
+      if (dx == -1 && dy == -1) return H[3 * plane + yj * Nx + xj];
+      if (dx == -1 && dy == 1) return H[4 * plane + yi * Nx + xj];  // i=(x+1,y), j=(x,y+1)
+      if (dx == 1 && dy == -1) return H[4 * plane + yj * Nx + xi];  // i=(x,y+1), j=(x+1,y)
+    }
+    return 0.0;
   }
   // A_ij
   __device__ double2 a(int xi, int yi, int xj, int yj) const {
@@ -109,12 +132,10 @@ struct Orig {
     const int dx = xj - xi, dy = yj - yi;
     if (dx == 0 && dy == 0) av = D[yi * Nx + xi];
     else if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) {
-      int idx;
-      bool fwd;
-      const int k = bond(xi, yi, xj, yj, idx, fwd);
-      if (k) {
-        av.x = -H[(size_t)k * Nx * Ny + idx];
-        if (sb) { const double2 t = bond_value(sb, k, idx, fwd); av.x -= t.x; av.y -= t.y; }
+      av.x = -hval(xi, yi, xj, yj);
+      if constexpr (BONDS) {
+        const double2 t = bond_value(sb, xi, yi, xj, yj);
+        av.x -= t.x; av.y -= t.y;
       }
     }
     if (contacts && dy == 0) {
@@ -129,11 +150,11 @@ struct Orig {
   __device__ double2 s(int xi, int yi, int xj, int yj) const {
     double2 sv = zero2();
     if (scat && xi == xj && yi == yj) sv = D[Nx * Ny + yi * Nx + xi];
-    if (slb && (xi != xj || yi != yj)) {
-      int idx;
-      bool fwd;
-      const int k = bond(xi, yi, xj, yj, idx, fwd);
-      if (k) { const double2 u = bond_value(slb, k, idx, fwd); sv.x += u.x; sv.y += u.y; }
+    if constexpr (BONDS) {
+      if (xi != xj || yi != yj) {
+        const double2 u = bond_value(slb, xi, yi, xj, yj);
+        sv.x += u.x; sv.y += u.y;
+      }
     }
     if (contacts && yi == yj) {
       if (yi == 0) { const double2 u = sless[xi * Nx + xj]; sv.x += u.x; sv.y += u.y; }
@@ -203,13 +224,14 @@ __device__ __forceinline__ void write_blk(double2* X, int b, int r, int c, bool 
 // row/column (local [S ; B] index): the block of a source cluster's stored U
 // (or R) when both indices come from that source, else the original A (or
 // Sigma<) between the two mesh nodes.
-struct Front {
+template <bool BONDS>
+struct FrontT {
   const int* node;     // LDS: (y << 16) | x
   const int* srcpos;   // LDS: (source << 24) | position
   const double2* U0;
   const double2* U1;
   int ld0, ld1;
-  Orig o;
+  OrigT<BONDS> o;
   int sym;             // bit 0: sources hold U as a packed lower triangle, bit 1: R likewise
 
   __device__ double2 a(int r, int c) const {
@@ -829,7 +851,7 @@ __device__ __forceinline__ void trsm_right_unit_lower(LDS& L, double2* FA, doubl
   }
 }
 
-template <int RPT, int TC, int CM, int NT, int MAXN>
+template <int RPT, int TC, int CM, int NT, int MAXN, bool BONDS = false>
 __global__ __launch_bounds__(NT, (TC == kTileWg || NT == 512) ? 2 : 3) void k_stage(StageArgs a) {
   // panel columns held in registers (the eight-wave form, at two waves per
   // SIMD, has the registers for twice the panel width with four rows a thread)
@@ -856,8 +878,8 @@ __global__ __launch_bounds__(NT, (TC == kTileWg || NT == 512) ? 2 : 3) void k_st
     }
     for (int k = tid; k < s; k += NT) L.perm[k] = k;
     __syncthreads();
-    const Front fr{L.node, L.srcpos, pool + E.src0, pool + E.src1, E.ld0, E.ld1,
-                   Orig{a.H, a.contacts ? a.sigma + (size_t)e * 2 * a.Nx * a.Nx : nullptr,
+    const FrontT<BONDS> fr{L.node, L.srcpos, pool + E.src0, pool + E.src1, E.ld0, E.ld1,
+                   OrigT<BONDS>{a.H, a.contacts ? a.sigma + (size_t)e * 2 * a.Nx * a.Nx : nullptr,
                         a.contacts ? a.sless + (size_t)e * 2 * a.Nx * a.Nx : nullptr,
                         pool + a.onsite_off, a.Nx, a.Ny, a.nst, a.sscat != nullptr, a.contacts,
                         a.sbond ? a.sbond + (size_t)e * (a.nst - 1) * a.Nx * a.Ny * 2 : nullptr,
@@ -1237,8 +1259,17 @@ __global__ __launch_bounds__(NT, 3) void k_final_gj(StageArgs a, OutArgs o) {
     hipLaunchKernelGGL((k_stage<R, T, C, kThreads, kThreads * R>), dim3(grid), dim3(kThreads), 0, st, a); \
     return hipGetLastError();                                                                 \
   }
+// Solves with stencil-pattern scattering self-energies run the 32x32 wave
+// tile with 4M products (or the eight-wave form) only.
+#define FIND_LAUNCH_BONDS(R, NTH)                                                              \
+  if (a.sbond) {                                                                              \
+    if (tc != 0 || cm != 0) return hipErrorInvalidValue;                                      \
+    hipLaunchKernelGGL((k_stage<R, 0, 0, NTH, NTH * R, true>), dim3(grid), dim3(NTH), 0, st, a); \
+    return hipGetLastError();                                                                 \
+  }
 #if FIND_TU == 1 || FIND_TU == 2
 hipError_t FIND_CAT(launch_stage_r, FIND_TU)(const StageArgs& a, int tc, int cm, int grid, hipStream_t st) {
+  FIND_LAUNCH_BONDS(FIND_TU, kThreads)
   FIND_LAUNCH_STAGE(FIND_TU, 0, 0) FIND_LAUNCH_STAGE(FIND_TU, 1, 0) FIND_LAUNCH_STAGE(FIND_TU, 2, 0) FIND_LAUNCH_STAGE(FIND_TU, 3, 0)
   FIND_LAUNCH_STAGE(FIND_TU, 0, 1) FIND_LAUNCH_STAGE(FIND_TU, 1, 1) FIND_LAUNCH_STAGE(FIND_TU, 2, 1) FIND_LAUNCH_STAGE(FIND_TU, 3, 1)
   FIND_LAUNCH_STAGE(FIND_TU, kTileWg, 0) FIND_LAUNCH_STAGE(FIND_TU, kTileWg, 1)
@@ -1247,6 +1278,8 @@ hipError_t FIND_CAT(launch_stage_r, FIND_TU)(const StageArgs& a, int tc, int cm,
 #endif
 #if FIND_TU == 3
 hipError_t launch_stage_r48(const StageArgs& a, int rpt, int tc, int cm, int grid, hipStream_t st) {
+  if (rpt == 4) { FIND_LAUNCH_BONDS(4, kThreads) }
+  if (rpt == 8) { FIND_LAUNCH_BONDS(8, kThreads) }
   if (rpt == 4) { FIND_LAUNCH_STAGE(4, 0, 0) FIND_LAUNCH_STAGE(4, 0, 1) }
   if (rpt == 8) { FIND_LAUNCH_STAGE(8, 0, 0) FIND_LAUNCH_STAGE(8, 0, 1) }
   return hipErrorInvalidValue;
@@ -1255,6 +1288,7 @@ hipError_t launch_stage_r48(const StageArgs& a, int rpt, int tc, int cm, int gri
 #if FIND_TU == 5
 // one wave per front (fronts of at most kWaveMaxFront nodes)
 hipError_t launch_stage_w(const StageArgs& a, int rpt, int cm, int grid, hipStream_t st) {
+  if (a.sbond) return hipErrorInvalidValue;   // (bond self-energies: four- and eight-wave forms only)
 #define FIND_LAUNCH_W(R, C)                                                                    \
   if (rpt == R && cm == C) {                                                                  \
     hipLaunchKernelGGL((k_stage<R, 0, C, 64, kWaveMaxFront>), dim3(grid), dim3(64), 0, st, a); \
@@ -1268,6 +1302,11 @@ hipError_t launch_stage_w(const StageArgs& a, int rpt, int cm, int grid, hipStre
 #if FIND_TU == 7
 // eight waves per front (one workgroup per CU, 256 VGPRs per lane)
 hipError_t launch_stage_w8(const StageArgs& a, int rpt, int cm, int grid, hipStream_t st) {
+  const int tc = 0;   // (the eight-wave form has one wave tile)
+  if (rpt == 1) { FIND_LAUNCH_BONDS(1, kEightWaveThreads) }
+  if (rpt == 2) { FIND_LAUNCH_BONDS(2, kEightWaveThreads) }
+  if (rpt == 4) { FIND_LAUNCH_BONDS(4, kEightWaveThreads) }
+  if (rpt == 8) { FIND_LAUNCH_BONDS(8, kEightWaveThreads) }
 #define FIND_LAUNCH_W8(R, C)                                                                   \
   if (rpt == R && cm == C) {                                                                  \
     hipLaunchKernelGGL((k_stage<R, 0, C, kEightWaveThreads, kEightWaveThreads * R>), dim3(grid), dim3(kEightWaveThreads), 0, st, a); \
@@ -1282,6 +1321,7 @@ hipError_t launch_stage_w8(const StageArgs& a, int rpt, int cm, int grid, hipStr
 #if FIND_TU == 6
 // two waves per front (fronts of at most kTwoWaveMaxFront nodes)
 hipError_t launch_stage_w2(const StageArgs& a, int rpt, int cm, int grid, hipStream_t st) {
+  if (a.sbond) return hipErrorInvalidValue;
 #define FIND_LAUNCH_W2(R, C)                                                                   \
   if (rpt == R && cm == C) {                                                                  \
     hipLaunchKernelGGL((k_stage<R, 0, C, 128, kTwoWaveMaxFront>), dim3(grid), dim3(128), 0, st, a); \
@@ -1330,5 +1370,6 @@ hipError_t launch_final_w(const StageArgs& a, const OutArgs& o, int rpt, int gri
 }
 #endif
 #undef FIND_LAUNCH_STAGE
+#undef FIND_LAUNCH_BONDS
 
 }  // namespace findmi

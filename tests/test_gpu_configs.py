@@ -386,13 +386,15 @@ def test_profiling_counts_launches_and_flops():
         assert abs(fl - plan.flops_per_energy() * E.size) <= 1e-9 * fl, kw
 
 
-@pytest.mark.parametrize("Nx,Ny,stencil,leaf", [(16, 12, 5, 4), (13, 10, 9, 2), (20, 24, 5, 8), (12, 17, 9, 4)])
+@pytest.mark.parametrize("Nx,Ny,stencil,leaf", [(16, 12, 5, 4), (13, 10, 9, 2), (20, 24, 5, 8), (12, 17, 9, 4),
+                                                (1030, 2, 5, 8)])
 def test_bond_scattering_against_dense(Nx, Ny, stencil, leaf):
     """Stencil-pattern (nearest-neighbour) scattering self-energies on top of
     diagonal ones that differ per energy and node: with no symmetry between
     a bond's two directions in the general form, symmetric in the symmetric
     form; against the dense oracle with bond outputs, in one pass and in
-    passes of two energies over two energy groups."""
+    passes of two energies over two energy groups.  The 1030 x 2 mesh has
+    fronts beyond 2048 nodes (the eight-wave bond instances)."""
     f = find()
     E = np.array([0.41 + 1e-6j, -1.9 + 1e-4j, 1.3 + 1e-3j])
     prob = inputs.make_problem(Nx, Ny, stencil, vmax=1.0, seed=Nx * 7 + Ny, energies=E, fL=1.0, fR=0.3)
@@ -411,3 +413,45 @@ def test_bond_scattering_against_dense(Nx, Ny, stencil, leaf):
             out = f.run_problem(plan, p, want_bonds=True)
             w = compare(out, ref, p, tol=SYM_TOL if sym else TOL, label=f"bond scattering {Nx}x{Ny} sym={sym} {kw}")
             print(f"bond scattering {Nx}x{Ny}/{stencil} sym={sym} {kw}: worst normwise {w['norm']:.2e}")
+
+
+@pytest.mark.parametrize("preset,nE,key,tol", [("c3_128x128", 256, "128x128/5/8/fp64/4m/scat", TOL),
+                                               ("c5_512x512", 8, None, TOL_LARGE),
+                                               ("wide_1100x4", 2, None, TOL)])
+def test_bond_scattering_hopping_rescaling_at_full_size(preset, nE, key, tol):
+    """A property that holds at any size: a stencil-pattern scattering
+    self-energy equal to c times the hopping on every bond (both directions,
+    Sigma<_b = 0) gives A = E I - (1 + c) H off the diagonal, the same matrix
+    as the hopping rescaled by 1 + c with no bond term.  At 128 x 128 with 256
+    energies in the tiles bench.py --scattering-bonds runs, at 512 x 512
+    9-point, and on a 1100 x 4 mesh whose fronts beyond 2048 nodes run the
+    eight-wave bond instances; on top of diagonal self-energies that differ
+    per energy and node."""
+    f = find()
+    c = 0.15
+    if preset == "wide_1100x4":
+        prob = inputs.make_problem(1100, 4, 5, vmax=1.0, seed=11, energies=np.array([0.37 + 1e-6j, -1.2 + 1e-3j]),
+                                   fL=1.0, fR=0.2)
+    else:
+        prob = inputs.make_preset(preset, n_energies=nE)
+    Nx, Ny, st = prob["Nx"], prob["Ny"], prob["stencil"]
+    sd, sld = inputs.scattering_self_energies_varied(Nx, Ny, nE, seed=3)
+    nbp = 2 if st == 5 else 4
+    # bond plane p holds the bond of H's plane p + 1, two directions
+    sb = np.broadcast_to((c * prob["H"][1:nbp + 1])[None, :, :, :, None], (nE, nbp, Ny, Nx, 2)).astype(np.complex128)
+    slb = np.zeros_like(sb)
+    H2 = prob["H"].copy()
+    H2[1:] *= 1.0 + c
+    plan = f.Plan(Nx, Ny, st, scattering=True)
+    if key is not None:
+        tuned(f, plan, key)
+    if preset == "wide_1100x4":
+        assert plan.summary()["max_n"] > 2048 and 7 in plan.tiles()   # eight-wave-only stages
+    with_bonds = f.run_problem(plan, dict(prob, sigma_d=sd, sigma_less_d=sld, sigma_b=sb, sigma_less_b=slb))
+    rescaled = f.run_problem(plan, dict(prob, H=H2, sigma_d=sd, sigma_less_d=sld))
+    plain = f.run_problem(plan, dict(prob, sigma_d=sd, sigma_less_d=sld), want_bonds=False)
+    assert nrel(with_bonds["diag_G"], plain["diag_G"]) > 1e-3     # the bond term matters
+    for k in ("diag_G", "diag_Gless", "bond_G", "bond_Gless"):
+        e = nrel(with_bonds[k], rescaled[k])
+        print(f"{preset} bond rescaling {k}: normwise {e:.2e}")
+        assert e <= tol, (preset, k, e)

@@ -149,6 +149,14 @@ def test_scattering_entry_points_reject_the_other_kind_of_plan():
     o = find.PlanOpts(leaf=8, scattering=2)
     h = ctypes.c_void_p()
     assert L.find_plan_create(6, 6, 5, ctypes.byref(o), ctypes.byref(h)) == find.FIND_E_ARG
+    # find_solve_scattering_bonds: a plain plan, a missing bond array, 3M
+    # complex products (the bond reads are compiled for 4M only)
+    d13 = [ctypes.c_void_p(16)] * 13
+    assert L.find_solve_scattering_bonds(pp.handle, 1, *d13, None) == find.FIND_E_ARG
+    assert L.find_solve_scattering_bonds(sp.handle, 1, *d13[:6], None, *d13[7:], None) == find.FIND_E_ARG
+    assert L.find_solve_scattering_bonds(sp.handle, 1, *d13[:7], None, *d13[8:], None) == find.FIND_E_ARG
+    p3 = find.Plan(6, 6, 5, scattering=True, complex_mode=find.CPLX_3M)
+    assert L.find_solve_scattering_bonds(p3.handle, 1, *d13, None) == find.FIND_E_UNSUPPORTED
 
 
 def test_tile_and_complex_mode_options():
@@ -473,6 +481,11 @@ def test_solve_rejects_scattering_inputs_for_a_plain_plan():
     plan = find.Plan(6, 6, 5)
     with pytest.raises(ValueError):
         find.solve(plan, None, None, None, None, None, None, sigma_d=object(), sigma_less_d=object())
+    with pytest.raises(ValueError):
+        find.solve(plan, None, None, None, None, None, None, sigma_b=object(), sigma_less_b=object())
+    with pytest.raises(ValueError):   # the two bond arrays go together
+        find.solve(find.Plan(6, 6, 5, scattering=True), None, None, None, None, None, None,
+                   sigma_d=object(), sigma_less_d=object(), sigma_b=object())
 
 
 @pytest.mark.parametrize("Nx,Ny,stencil,leaf", [(16, 16, 5, 2), (12, 10, 5, 2), (9, 14, 5, 2), (8, 8, 5, 1),

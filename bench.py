@@ -343,8 +343,9 @@ def main() -> int:
                    "launch": "eager" if args.no_graph else "hipGraph replay per batch",
                    "stage_tiles": "".join(str(t) for t in tiles),
                    "stage_tiles_from": tiles_from,
-                   **({"stage_tiles_note": "with bond self-energies every non-final stage runs configuration 0 "
-                                           "(7 where only the eight-wave form fits); the final stage as listed"}
+                   **({"stage_tiles_note": "with bond self-energies, non-final stages whose tile is 1, 2, 3 "
+                                           "or 6 run configuration 0 instead (7 where only the eight-wave form "
+                                           "fits); the others as listed"}
                       if args.scattering_bonds else {}),
                    "autotune_s": round(tune_s, 3) if tiles_from == "autotune" else None},
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},

@@ -737,11 +737,15 @@ find_status enqueue_solve(find_plan plan, DevState* d, const SolveBufs& b, int n
           d->ev_flops[d->ev_used] = s2.flops_per_energy * gn;
           HIPCHK(hipEventRecord(d->ev[2 * d->ev_used], sg));
         }
-        // solves with stencil-pattern scattering self-energies take the 32x32
-        // wave tile (the eight-wave form where it is the only one), the
-        // configurations compiled with the bond reads
-        const int tck = (a.sbond && s2.phase != PH_FINAL) ? ((plan->tile_mask[k] & 1) ? 0 : kTileEight)
-                                                          : plan->tiles[k];
+        // solves with stencil-pattern scattering self-energies run the
+        // configurations compiled with the bond reads (the 32x32 wave tile of
+        // the one-, two-, four- and eight-wave forms): the stage's own where
+        // it is one of them, else configuration 0 (the eight-wave form where
+        // it is the only one)
+        const int tk = plan->tiles[k];
+        const bool bond_cfg = tk == 0 || tk == kTileWave || tk == kTileTwoWave || tk == kTileEight;
+        const int tck = (a.sbond && s2.phase != PH_FINAL && !bond_cfg)
+                            ? ((plan->tile_mask[k] & 1) ? 0 : kTileEight) : tk;
         const hipError_t he = launch_stage_k(plan, d, int(k), a, o, tck, sg);
         if (he != hipSuccess) return fail(FIND_E_DEVICE, std::string("stage launch: ") + hipGetErrorString(he));
         if (b.profiling) ++d->launch_count;

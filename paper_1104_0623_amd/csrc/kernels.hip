@@ -1288,7 +1288,12 @@ hipError_t launch_stage_r48(const StageArgs& a, int rpt, int tc, int cm, int gri
 #if FIND_TU == 5
 // one wave per front (fronts of at most kWaveMaxFront nodes)
 hipError_t launch_stage_w(const StageArgs& a, int rpt, int cm, int grid, hipStream_t st) {
-  if (a.sbond) return hipErrorInvalidValue;   // (bond self-energies: four- and eight-wave forms only)
+  if (a.sbond) {
+    if (cm != 0) return hipErrorInvalidValue;
+    if (rpt == 1) { hipLaunchKernelGGL((k_stage<1, 0, 0, 64, kWaveMaxFront, true>), dim3(grid), dim3(64), 0, st, a); return hipGetLastError(); }
+    if (rpt == 2) { hipLaunchKernelGGL((k_stage<2, 0, 0, 64, kWaveMaxFront, true>), dim3(grid), dim3(64), 0, st, a); return hipGetLastError(); }
+    return hipErrorInvalidValue;
+  }
 #define FIND_LAUNCH_W(R, C)                                                                    \
   if (rpt == R && cm == C) {                                                                  \
     hipLaunchKernelGGL((k_stage<R, 0, C, 64, kWaveMaxFront>), dim3(grid), dim3(64), 0, st, a); \
@@ -1321,7 +1326,12 @@ hipError_t launch_stage_w8(const StageArgs& a, int rpt, int cm, int grid, hipStr
 #if FIND_TU == 6
 // two waves per front (fronts of at most kTwoWaveMaxFront nodes)
 hipError_t launch_stage_w2(const StageArgs& a, int rpt, int cm, int grid, hipStream_t st) {
-  if (a.sbond) return hipErrorInvalidValue;
+  if (a.sbond) {
+    if (cm != 0) return hipErrorInvalidValue;
+    if (rpt == 1) { hipLaunchKernelGGL((k_stage<1, 0, 0, 128, kTwoWaveMaxFront, true>), dim3(grid), dim3(128), 0, st, a); return hipGetLastError(); }
+    if (rpt == 2) { hipLaunchKernelGGL((k_stage<2, 0, 0, 128, kTwoWaveMaxFront, true>), dim3(grid), dim3(128), 0, st, a); return hipGetLastError(); }
+    return hipErrorInvalidValue;
+  }
 #define FIND_LAUNCH_W2(R, C)                                                                   \
   if (rpt == R && cm == C) {                                                                  \
     hipLaunchKernelGGL((k_stage<R, 0, C, 128, kTwoWaveMaxFront>), dim3(grid), dim3(128), 0, st, a); \

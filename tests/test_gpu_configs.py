@@ -386,6 +386,24 @@ def test_profiling_counts_launches_and_flops():
         assert abs(fl - plan.flops_per_energy() * E.size) <= 1e-9 * fl, kw
 
 
+def one_and_two_wave_tiles(f, plan):
+    """Every stage that has the one-wave (configuration 4), else the two-wave
+    form (5) set to it; the others keep their tile."""
+    tiles = list(plan.tiles())
+    for k in range(len(tiles)):
+        for t in (4, 5):
+            trial = tiles[:k] + [t] + tiles[k + 1:]
+            try:
+                plan.set_tiles(trial)
+            except f.FindError:
+                continue
+            tiles = trial
+            break
+    plan.set_tiles(tiles)
+    assert 4 in tiles or 5 in tiles
+    return "".join(str(t) for t in tiles)
+
+
 @pytest.mark.parametrize("Nx,Ny,stencil,leaf", [(16, 12, 5, 4), (13, 10, 9, 2), (20, 24, 5, 8), (12, 17, 9, 4),
                                                 (1030, 2, 5, 8)])
 def test_bond_scattering_against_dense(Nx, Ny, stencil, leaf):
@@ -393,7 +411,8 @@ def test_bond_scattering_against_dense(Nx, Ny, stencil, leaf):
     diagonal ones that differ per energy and node: with no symmetry between
     a bond's two directions in the general form, symmetric in the symmetric
     form; against the dense oracle with bond outputs, in one pass and in
-    passes of two energies over two energy groups.  The 1030 x 2 mesh has
+    passes of two energies over two energy groups, and with the one- and
+    two-wave forms on the stages that have them.  The 1030 x 2 mesh has
     fronts beyond 2048 nodes (the eight-wave bond instances)."""
     f = find()
     E = np.array([0.41 + 1e-6j, -1.9 + 1e-4j, 1.3 + 1e-3j])
@@ -408,8 +427,11 @@ def test_bond_scattering_against_dense(Nx, Ny, stencil, leaf):
         plain = dense.dense_solve(Nx, Ny, stencil, prob["H"], E, prob["sigma"], prob["sigma_less"],
                                   sigma_d=sd, sigma_less_d=sld)
         assert nrel(ref["diag_Gless"], plain["diag_Gless"]) > 1e-4   # the bond terms matter
-        for kw in ({}, dict(streams=2, max_energies=2)):
+        for kw in ({}, dict(streams=2, max_energies=2), dict(wave_forms=True)):
+            wave = kw.pop("wave_forms", False)
             plan = f.Plan(Nx, Ny, stencil, leaf=leaf, scattering=True, symmetric=sym, **kw)
+            if wave:
+                kw = dict(tiles=one_and_two_wave_tiles(f, plan))
             out = f.run_problem(plan, p, want_bonds=True)
             w = compare(out, ref, p, tol=SYM_TOL if sym else TOL, label=f"bond scattering {Nx}x{Ny} sym={sym} {kw}")
             print(f"bond scattering {Nx}x{Ny}/{stencil} sym={sym} {kw}: worst normwise {w['norm']:.2e}")

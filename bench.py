@@ -29,8 +29,8 @@ PRECISION = {"fp64": 0, "mixed": 1, "mixed-gless": 2}   # find_precision values
 # solve, from rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs (calibrated on a
 # plain copy; profiles/elim_kernels_c3_128x128_fp64.md).  Valid only for the
 # native sources (kernels, plan, C-ABI) they were measured on.
-TRAFFIC_BYTES_PER_LAUNCH = 31467747442.85
-TRAFFIC_KERNEL_SHA = "bc71f5c5e054dfa7"
+TRAFFIC_BYTES_PER_LAUNCH = 31470178020.38
+TRAFFIC_KERNEL_SHA = "d7bcad8cff15fdad"
 TRAFFIC_TILES = "445510763600105141418000"
 TRAFFIC_FORM = (0, 1)   # (symmetric form, energy groups) of the counter runs
 
